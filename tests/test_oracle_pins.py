@@ -1,0 +1,251 @@
+"""Pins of the oracle's iteration against what the paper and linear algebra fix.
+
+* P1  limit A^+ b (Section 1, the four cases) from an SVD pseudoinverse on tiny systems;
+* P2  x^k - A^+ b stays in range(A^T) (proof of Theorem 5), so x^k in range(A^T) when x^0 = 0;
+* P3  z^k - b_perp stays in range(A) and z^k -> b_perp = (I - A A^+) b (Lemma 4);
+* P4  with one row block and one column block the iteration is deterministic and equals the
+      closed form of the proof of Theorem 1;
+* P5  for general partitions the mean of x^k over independent streams matches that closed form
+      (Theorem 1, expectation);
+* P6  the block update is the weighted average of single-row/column projections (Section 2);
+* P7  s = m, t = n, alpha = 1 is REK (Section 2), checked against an independent REK loop;
+      z^0 = 0 keeps z = 0 (Section 2);
+* P9  the x-trajectory does not depend on the component of b in null(A^T);
+* P10 scaling A and b by a power of two changes no block and no bit of x;
+* P11 Theorem 5 / Remark 9: the mean-square error stays below the stated bound.
+"""
+import numpy as np
+import pytest
+
+from paper_2001_04179_amd import workloads as W
+
+
+def pinv_solution(A, b):
+    return np.linalg.pinv(A, rcond=1e-12) @ b
+
+
+def alpha_default(A, ro, co):
+    br, bc = W.beta_max(A, ro, co)
+    return 1.0 / max(br, bc)
+
+
+TINY = {
+    "overdetermined_inconsistent": (np.random.default_rng(10).standard_normal((12, 7)), 3, 2),
+    "underdetermined_consistent": (np.random.default_rng(11).standard_normal((7, 12)), 2, 3),
+    "rank_deficient_inconsistent": (
+        np.random.default_rng(12).standard_normal((10, 4)) @ np.random.default_rng(13).standard_normal((4, 8)), 3, 3),
+    "square_singular": (
+        np.random.default_rng(14).standard_normal((9, 5)) @ np.random.default_rng(15).standard_normal((5, 9)), 4, 2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TINY))
+def test_p1_limit_is_pinv_b(oracle_lib, name):
+    A, rt, ct = TINY[name]
+    m, n = A.shape
+    b = np.random.default_rng(99).standard_normal(m)  # a generic b: inconsistent unless A has full row rank
+    ro, co = W.contiguous_offsets(m, rt), W.contiguous_offsets(n, ct)
+    xp = pinv_solution(A, b)
+    out = oracle_lib.rebk_solve(A, ro, co, alpha_default(A, ro, co), 5, b, max_iter=200000, x_ref=xp, tol=1e-12)
+    assert out["status"] == 0, out["err"]
+    assert np.linalg.norm(out["x"] - xp) <= 1e-11 * np.linalg.norm(xp)
+
+
+def test_p2_x_stays_in_row_space(oracle_lib):
+    A, rt, ct = TINY["rank_deficient_inconsistent"]
+    m, n = A.shape
+    b = np.random.default_rng(5).standard_normal(m)
+    ro, co = W.contiguous_offsets(m, rt), W.contiguous_offsets(n, ct)
+    _, sv, Vt = np.linalg.svd(A)
+    V = Vt[: int(np.sum(sv > 1e-10 * sv[0]))].T
+    for k in (1, 10, 100, 1000):
+        x = oracle_lib.rebk_solve(A, ro, co, alpha_default(A, ro, co), 1, b, max_iter=k)["x"]
+        out_of_range = x - V @ (V.T @ x)
+        assert np.linalg.norm(out_of_range) <= 1e-13 * k * max(np.linalg.norm(x), 1.0)
+
+
+def test_p3_z_converges_to_b_perp(oracle_lib):
+    A, rt, ct = TINY["rank_deficient_inconsistent"]
+    m, n = A.shape
+    b = np.random.default_rng(6).standard_normal(m)
+    ro, co = W.contiguous_offsets(m, rt), W.contiguous_offsets(n, ct)
+    U, sv, _ = np.linalg.svd(A, full_matrices=False)
+    Q = U[:, : int(np.sum(sv > 1e-10 * sv[0]))]
+    b_perp = b - Q @ (Q.T @ b)
+    alpha = alpha_default(A, ro, co)
+    prev = None
+    for k in (10, 100, 1000, 5000):
+        z = oracle_lib.rebk_solve(A, ro, co, alpha, 2, b, max_iter=k)["z"]
+        d = z - b_perp
+        assert np.linalg.norm(d - Q @ (Q.T @ d)) <= 1e-13 * k * np.linalg.norm(b)   # z - b_perp in range(A)
+        err = np.linalg.norm(d)
+        if prev is not None:
+            assert err < prev
+        prev = err
+    assert prev <= 1e-10 * np.linalg.norm(b)
+
+
+def closed_form_x(A, b, x0, z0, alpha, k):
+    """x^k from the expectation recursion in the proof of Theorem 1:
+    x^k - A^+ b = M^k (x^0 - A^+ b) - alpha k M^k A^T z^0 / ||A||_F^2, M = I - alpha A^T A / ||A||_F^2."""
+    F2 = np.sum(A * A)
+    n = A.shape[1]
+    M = np.eye(n) - alpha * (A.T @ A) / F2
+    Mk = np.linalg.matrix_power(M, k)
+    xp = pinv_solution(A, b)
+    return xp + Mk @ (x0 - xp) - alpha * k * Mk @ (A.T @ z0) / F2
+
+
+def test_p4_single_block_closed_form(oracle_lib):
+    rng = np.random.default_rng(20)
+    A = rng.standard_normal((15, 6))
+    b = rng.standard_normal(15)
+    x0 = rng.standard_normal(6)
+    z0 = rng.standard_normal(15)
+    alpha = 1.3
+    F2 = np.sum(A * A)
+    for k in (1, 2, 5, 20, 60):
+        out = oracle_lib.rebk_solve(A, [0, 15], [0, 6], alpha, 0, b, x0=x0, z0=z0, max_iter=k)
+        ref = closed_form_x(A, b, x0, z0, alpha, k)
+        assert np.linalg.norm(out["x"] - ref) <= 1e-12 * np.linalg.norm(ref)
+        zref = np.linalg.matrix_power(np.eye(15) - alpha * (A @ A.T) / F2, k) @ z0
+        assert np.linalg.norm(out["z"] - zref) <= 1e-12 * np.linalg.norm(z0)
+
+
+def test_p5_expectation_matches_closed_form(oracle_lib):
+    """Theorem 1: E[x^k] follows the closed form for any partitions; 20000 independent streams."""
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((8, 6))
+    b = rng.standard_normal(8)
+    x0 = np.zeros(6)
+    ro, co = [0, 3, 5, 8], [0, 2, 3, 6]
+    alpha, k, N = 0.9, 3, 20000
+    xs = np.empty((N, 6))
+    for q in range(N):
+        xs[q] = oracle_lib.rebk_solve(A, ro, co, alpha, 1000 + q, b, max_iter=k, trace=False)["x"]
+    mean = xs.mean(axis=0)
+    se = xs.std(axis=0, ddof=1) / np.sqrt(N)
+    ref = closed_form_x(A, b, x0, b, alpha, k)
+    assert np.all(np.abs(mean - ref) <= 5.0 * se + 1e-12), (mean - ref) / se
+
+
+def test_p6_block_update_is_weighted_single_projections(oracle_lib):
+    rng = np.random.default_rng(22)
+    A = rng.standard_normal((20, 11))
+    b = rng.standard_normal(20)
+    x0 = rng.standard_normal(11)
+    z0 = rng.standard_normal(20)
+    ro, co = [0, 6, 13, 20], [0, 4, 7, 11]
+    alpha = 1.7
+    out = oracle_lib.rebk_solve(A, ro, co, alpha, 3, b, x0=x0, z0=z0, max_iter=1)
+    j, i = int(out["j"][0]), int(out["i"][0])
+    J = range(co[j], co[j + 1])
+    I = range(ro[i], ro[i + 1])
+    FJ = sum(A[:, l] @ A[:, l] for l in J)
+    FI = sum(A[l] @ A[l] for l in I)
+    z1 = z0.copy()
+    for l in J:
+        a = A[:, l]
+        omega = (a @ a) / FJ
+        z1 -= alpha * omega * (a @ z0) / (a @ a) * a
+    x1 = x0.copy()
+    for l in I:
+        a = A[l]
+        omega = (a @ a) / FI
+        x1 -= alpha * omega * (a @ x0 - b[l] + z1[l]) / (a @ a) * a
+    assert np.linalg.norm(out["z"] - z1) <= 1e-13 * np.linalg.norm(z1)
+    assert np.linalg.norm(out["x"] - x1) <= 1e-13 * np.linalg.norm(x1)
+
+
+def test_p7_rek_special_case(oracle_lib):
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((30, 12))
+    b = rng.standard_normal(30)
+    m, n = A.shape
+    K = 800
+    out = oracle_lib.rebk_solve(A, np.arange(m + 1), np.arange(n + 1), 1.0, 9, b, max_iter=K)
+    z, x = b.copy(), np.zeros(n)
+    for k in range(K):
+        j, i = int(out["j"][k]), int(out["i"][k])
+        col = A[:, j]
+        z = z - (col @ z) / (col @ col) * col
+        row = A[i]
+        x = x - (row @ x - b[i] + z[i]) / (row @ row) * row
+    assert np.linalg.norm(out["x"] - x) <= 1e-11 * np.linalg.norm(x)
+    assert np.linalg.norm(out["z"] - z) <= 1e-11 * np.linalg.norm(z)
+    # REK's column draw is proportional to the squared column norms
+    counts = np.bincount(out["j"], minlength=n)
+    assert counts.argmax() in np.argsort(np.sum(A * A, axis=0))[-4:]
+
+
+def test_p7_zero_z0_gives_rabk(oracle_lib):
+    rng = np.random.default_rng(24)
+    A = rng.standard_normal((25, 10))
+    xs = rng.standard_normal(10)
+    b = A @ xs  # consistent
+    ro, co = [0, 5, 10, 18, 25], [0, 3, 10]
+    out = oracle_lib.rebk_solve(A, ro, co, 1.0, 4, b, z0=np.zeros(25), max_iter=3000)
+    assert np.all(out["z"] == 0.0)
+    assert np.linalg.norm(out["x"] - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_p9_independent_of_null_space_component(oracle_lib):
+    S = W.type2(150, 40, rng_seed=31, noise=0.5, row_tau=15, col_tau=4, seed=2)
+    b_cons = S.A @ S.x_star
+    a = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=700)
+    c = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, b_cons, max_iter=700)
+    assert np.array_equal(a["j"], c["j"]) and np.array_equal(a["i"], c["i"])
+    assert np.linalg.norm(a["x"] - c["x"]) <= 1e-10 * np.linalg.norm(c["x"])
+    assert np.linalg.norm(a["z"] - c["z"] - (S.b - b_cons)) <= 1e-10 * np.linalg.norm(S.b)
+
+
+def test_p10_power_of_two_scaling_is_exact(oracle_lib):
+    S = W.type2(90, 33, rng_seed=32, noise=0.2, row_tau=10, col_tau=5, seed=8)
+    a = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=400)
+    c = oracle_lib.rebk_solve(4.0 * S.A, S.row_off, S.col_off, S.alpha, S.seed, 4.0 * S.b, max_iter=400)
+    assert np.array_equal(a["j"], c["j"]) and np.array_equal(a["i"], c["i"])
+    assert np.array_equal(a["x"], c["x"])
+    assert np.array_equal(4.0 * a["z"], c["z"])
+
+
+def test_p11_mean_square_error_bound(oracle_lib):
+    """Remark 9 with alpha = 1 / beta_max and eps = 1/k: E||x^k - A^+ b||^2 <= the stated bound."""
+    rng = np.random.default_rng(25)
+    A = rng.standard_normal((40, 12))
+    b = rng.standard_normal(40)
+    ro, co = W.contiguous_offsets(40, 8), W.contiguous_offsets(12, 3)
+    br, bc = W.beta_max(A, ro, co)
+    bmax = max(br, bc)
+    alpha = 1.0 / bmax
+    F2 = np.sum(A * A)
+    sv = np.linalg.svd(A, compute_uv=False)
+    rho_hat = 1.0 - (2 * alpha - alpha * alpha * bmax) * sv[-1] ** 2 / F2
+    xp = pinv_solution(A, b)
+    U, _, _ = np.linalg.svd(A, full_matrices=False)
+    b_perp = b - U @ (U.T @ b)
+    k, N = 60, 400
+    eps = 1.0 / k
+    bound = (1 + eps) ** k * rho_hat ** k * (np.sum(xp ** 2)
+                                            + (1 + eps) * alpha ** 2 * br * np.sum((b - b_perp) ** 2) / (eps ** 2 * F2))
+    mse = np.mean([np.sum((oracle_lib.rebk_solve(A, ro, co, alpha, 500 + q, b, max_iter=k, trace=False)["x"] - xp) ** 2)
+                   for q in range(N)])
+    assert mse <= bound
+    # and the iteration does contract: the error after k steps is well below the initial error
+    assert mse < 0.5 * np.sum(xp ** 2)
+
+
+def test_dense_1000x100_converges(oracle_lib):
+    """The 1000 x 100 Gaussian system reaches relative error 1e-6 in a few hundred iterations."""
+    S = W.dense_gaussian_1000x100()
+    out = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=5000, x_ref=S.x_ref,
+                                tol=1e-6)
+    assert out["status"] == 0 and 150 <= out["iterations"] <= 1000
+
+
+def test_invalid_inputs_rejected(oracle_lib):
+    A = np.ones((4, 3))
+    b = np.ones(4)
+    with pytest.raises(ValueError):
+        oracle_lib.rebk_solve(A, [0, 4], [0, 3], -1.0, 0, b, max_iter=3)
+    with pytest.raises(ValueError):
+        oracle_lib.rebk_solve(np.zeros((4, 3)), [0, 4], [0, 3], 1.0, 0, b, max_iter=3)
