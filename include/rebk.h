@@ -1,0 +1,201 @@
+/*
+ * rebk.h -- C ABI of librebk.so, a gfx950 (MI355X) implementation of the
+ * randomized extended block Kaczmarz method (REBK) of Du, Si and Sun,
+ * "Randomized extended block Kaczmarz for solving least squares",
+ * arXiv:2001.04179.
+ *
+ * REBK (Section 2, Algorithm 1) approximates the minimum-norm least-squares
+ * solution A^+ b of any linear system A x = b (consistent or not, over- or
+ * underdetermined, full rank or not; Section 1).  Given partitions
+ * {I_1..I_s} of the rows and {J_1..J_t} of the columns and a stepsize
+ * alpha > 0, iteration k = 1, 2, ... does
+ *
+ *   j  ~ P(j) = ||A_{:,J_j}||_F^2 / ||A||_F^2
+ *   z <- z - alpha / ||A_{:,J_j}||_F^2 * A_{:,J_j} (A_{:,J_j}^T z)
+ *   i  ~ P(i) = ||A_{I_i,:}||_F^2 / ||A||_F^2
+ *   x <- x - alpha / ||A_{I_i,:}||_F^2 * A_{I_i,:}^T (A_{I_i,:} x - b_{I_i} + z_{I_i})
+ *
+ * with z^0 = b and x^0 = 0 in the paper's experiments (Section 3).  x^k
+ * converges in mean square to A^+ b when z^0 is in b + range(A), x^0 is in
+ * range(A^T) and 0 < alpha < 2 / beta_max (Theorem 5, Remark 9).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named *_dev are device pointers (HIP global memory) owned by
+ *    the caller; the library never frees them.  Host pointers are named
+ *    without the suffix.  Vectors are dense and contiguous.
+ *  - Block partitions are contiguous: block i holds rows
+ *    row_offsets[i] .. row_offsets[i+1]-1 (offsets strictly increasing from
+ *    0 to m); likewise for columns.  Section 3 uses equal blocks of size tau
+ *    with a smaller last block.
+ *  - Random draws: iteration k (1-based) draws both blocks from one
+ *    Philox4x64-10 output (Salmon et al., SC'11) with counter
+ *    (k-1, system, 0, 0) and key (seed, 0); word 0 picks the column block
+ *    and word 1 the row block.  The top 53 bits of a word are compared
+ *    against cumulative integer thresholds floor(C_j / C_total * 2^53) of
+ *    the prefix sums C_j of the block weights (last threshold 2^53): the
+ *    block drawn is the first whose threshold exceeds them.  Block weights
+ *    are summed in FP64 in a fixed order (per matrix row, squares of the
+ *    entries in ascending column order; then rows in ascending order;
+ *    every product rounded before it is added), so the block sequence is
+ *    reproducible bit for bit by any implementation of the same rules.
+ *  - Work is enqueued on the handle's HIP stream.  Calls that return
+ *    results in host memory synchronize that stream before returning.
+ *  - Return codes: REBK_OK (0) or a rebk_status_t.  Negative codes are
+ *    failures; the message of the last failure on the calling thread is
+ *    returned by rebk_last_error().  REBK_ERR_INVALID leaves outputs
+ *    untouched.  After REBK_ERR_HIP or REBK_ERR_TIMEOUT the handle must be
+ *    destroyed.  Nothing in the library aborts or exits the process.
+ *  - A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef REBK_H
+#define REBK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rebk_handle *rebk_handle_t;
+
+/* Element types.  REBK_F64 and REBK_F32 are accepted for the caller's A;
+ * every type is accepted for the stored panels; the iterates are FP64. */
+typedef enum {
+    REBK_F64 = 0,
+    REBK_F32 = 1,
+    REBK_BF16 = 2,
+    REBK_F16 = 3
+} rebk_dtype_t;
+
+typedef enum {
+    REBK_OK = 0,              /* stopped on the tolerance, or ran max_iter without a stop rule */
+    REBK_NOT_CONVERGED = 1,   /* max_iter reached before the tolerance; outputs are written */
+    REBK_DIVERGED = 2,        /* the error or residual became non-finite or grew 1e6-fold */
+    REBK_ERR_INVALID = -1,    /* bad argument; nothing was written */
+    REBK_ERR_HIP = -2,        /* a HIP runtime call failed */
+    REBK_ERR_OOM = -3,        /* device allocation failed */
+    REBK_ERR_TIMEOUT = -4     /* a grid barrier of the persistent kernel exceeded its spin limit */
+} rebk_status_t;
+
+/* Which kernel runs the iterations. */
+typedef enum {
+    REBK_KERNEL_AUTO = 0,     /* GRID for large blocks, WORKGROUP otherwise */
+    REBK_KERNEL_WORKGROUP = 1,/* one workgroup runs the whole solve (small systems) */
+    REBK_KERNEL_GRID = 2      /* one persistent cooperative grid, one grid barrier per iteration */
+} rebk_kernel_t;
+
+typedef struct {
+    int32_t status;      /* rebk_status_t of the solve */
+    int32_t kernel;      /* rebk_kernel_t that ran */
+    int64_t iterations;  /* iterations performed in this call (k counts from k0) */
+    double rel_err;      /* ||x - x_ref|| / ||x_ref|| at the last check (x_ref mode),
+                            max(||b - z - A x|| / ||b||, ||A^T z|| / (||A||_F ||b||)) (residual
+                            mode), or -1 if nothing was checked */
+    double time_ms;      /* device time of the iterations, HIP events on the handle's stream */
+} rebk_result_t;
+
+/* Options of rebk_solve_ex.  Zero-initialise and set what you need. */
+typedef struct {
+    const double *b_dev;     /* right-hand side, m entries (required) */
+    const double *x0_dev;    /* initial x, n entries; NULL means 0 (Section 3) */
+    const double *z0_dev;    /* initial z, m entries; NULL means b (Section 3) */
+    int64_t k0;              /* iterations already done: this call runs k0+1, k0+2, ...
+                                (resuming with the x, z of an earlier call continues that
+                                run exactly) */
+    int64_t max_iter;        /* at most this many iterations in this call (> 0) */
+    const double *x_ref_dev; /* if not NULL, stop at the first checked k with
+                                ||x^k - x_ref|| / ||x_ref|| < tol (a reference solution,
+                                typically A^+ b; the experiments of Section 3 stop on the
+                                true error) */
+    double tol;              /* tolerance; <= 0 runs exactly max_iter iterations */
+    int64_t check_every;     /* check the stop rule every this many iterations; 0 means 1
+                                with x_ref and 256 in residual mode */
+    double *x_out_dev;       /* result x, n entries (required; may alias x0_dev) */
+    double *z_out_dev;       /* result z, m entries, or NULL (may alias z0_dev) */
+    int32_t *trace_j_dev;    /* if not NULL: 0-based column block of each iteration (max_iter) */
+    int32_t *trace_i_dev;    /* if not NULL: 0-based row block of each iteration (max_iter) */
+    int32_t kernel;          /* rebk_kernel_t */
+    int32_t grid_wgs;        /* GRID kernel: workgroups (0 = one per compute unit) */
+} rebk_solve_opts_t;
+
+/*
+ * Create a solver for A (m x n, row-major, leading dimension lda >= n,
+ * element type a_dtype in {REBK_F64, REBK_F32}) with the given contiguous
+ * partitions (host arrays of s+1 and t+1 offsets), stepsize alpha > 0 and
+ * Philox seed (Algorithm 1).
+ *
+ * A is copied into library-owned device panels stored as panel_dtype:
+ * every row block as an n x |I_i| column-major panel and every column block
+ * as an m x |J_j| row-major panel, so that both block reads of an iteration
+ * are contiguous.  A may be freed when the call returns.  The FP64 block
+ * weights ||A_{I_i,:}||_F^2 and ||A_{:,J_j}||_F^2 of the stored values and the
+ * sampling thresholds are computed here (the only host synchronisation).
+ *
+ * stream is a hipStream_t (NULL for the default stream).  Errors:
+ * REBK_ERR_INVALID for bad sizes, offsets, dtype or alpha, or if A has a
+ * non-finite entry or ||A||_F = 0; REBK_ERR_OOM; REBK_ERR_HIP.
+ */
+int rebk_create(rebk_handle_t *out, const void *A_dev, int32_t a_dtype, int32_t panel_dtype,
+                int64_t m, int64_t n, int64_t lda,
+                const int64_t *row_offsets, int64_t s,
+                const int64_t *col_offsets, int64_t t,
+                double alpha, uint64_t seed, void *stream);
+
+/* Release the handle and its device memory (NULL is ignored). */
+void rebk_destroy(rebk_handle_t h);
+
+/*
+ * Solve with the plain interface: z^0 = b, x^0 = x0_dev (NULL means 0), at
+ * most max_iter iterations, residual stop rule
+ *   ||b - z - A x|| <= tol ||b||  and  ||A^T z|| <= tol ||A||_F ||b||
+ * checked every 256 iterations (z converges to (I - A A^+) b, Lemma 4, and
+ * then A x converges to A A^+ b).  x_out_dev receives x (n entries).
+ * res (host, may be NULL) receives the result.  Returns the solve status.
+ */
+int rebk_solve(rebk_handle_t h, const double *b_dev, const double *x0_dev, double *x_out_dev,
+               double tol, int64_t max_iter, rebk_result_t *res);
+
+/* Solve with every option (see rebk_solve_opts_t).  Returns the solve status. */
+int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t *opts, rebk_result_t *res);
+
+/*
+ * Copy the FP64 block weights to host arrays w_row (s entries, ||A_{I_i,:}||_F^2)
+ * and w_col (t entries, ||A_{:,J_j}||_F^2); either may be NULL.
+ */
+int rebk_get_weights(rebk_handle_t h, double *w_row, double *w_col);
+
+/* Copy the cumulative 53-bit sampling thresholds (s and t entries) to host arrays. */
+int rebk_get_thresholds(rebk_handle_t h, uint64_t *T_row, uint64_t *T_col);
+
+/* Sizes of the handle: m, n, s, t, the largest row block and the largest column block. */
+int rebk_get_info(rebk_handle_t h, int64_t *m, int64_t *n, int64_t *s, int64_t *t,
+                  int64_t *max_row_block, int64_t *max_col_block);
+
+/*
+ * Run only the block sampler of the handle on the device for iterations
+ * k0+1 .. k0+count of system `system`: j_out_dev[q] and i_out_dev[q]
+ * (int32, count entries each) receive the 0-based blocks of iteration
+ * k0+q+1.  Synchronizes the stream.
+ */
+int rebk_sample_blocks(rebk_handle_t h, uint64_t system, int64_t k0, int64_t count,
+                       int32_t *j_out_dev, int32_t *i_out_dev);
+
+/*
+ * Philox4x64-10 on the device, as used by the sampler: for q in [0, count),
+ * out_dev[4q .. 4q+3] = Philox(counter = (c0 + q, c1, c2, c3), key = (k0, k1)).
+ * stream as in rebk_create.  Synchronizes the stream.
+ */
+int rebk_philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                       uint64_t k0, uint64_t k1, int64_t count, uint64_t *out_dev, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *rebk_last_error(void);
+
+/* Library version string. */
+const char *rebk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REBK_H */

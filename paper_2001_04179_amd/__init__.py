@@ -1,0 +1,199 @@
+"""REBK on MI355X: Python binding of ``librebk.so``.
+
+Randomized extended block Kaczmarz (Du, Si, Sun, arXiv:2001.04179, Section 2, Algorithm 1) for
+the minimum-norm least-squares solution A^+ b.  Every step of the method runs in the HIP
+library; this module only marshals arguments.  PyTorch supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+__all__ = ["Solver", "SolveResult", "philox4x64_10", "contiguous_offsets", "RebkError", "version"]
+
+RebkError = N.RebkError
+
+
+def version() -> str:
+    return N.load().rebk_version().decode()
+
+
+def contiguous_offsets(total: int, tau: int) -> np.ndarray:
+    """Offsets of the contiguous partition into blocks of size tau, the last one smaller
+    (Section 3): [0, tau, 2 tau, ..., total]."""
+    if total <= 0 or tau <= 0:
+        raise ValueError("total and tau must be positive")
+    off = list(range(0, total, tau)) + [total]
+    return np.asarray(off, dtype=np.int64)
+
+
+@dataclass
+class SolveResult:
+    status: str
+    code: int
+    kernel: str
+    iterations: int
+    rel_err: float
+    time_ms: float
+
+
+def _dev_ptr(t: Optional[torch.Tensor], n: int, name: str, dtype=torch.float64):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor with {n} entries")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """``rebk_create`` on a CUDA tensor A (m x n, float64 or float32, row-major).
+
+    row_offsets / col_offsets: the contiguous partitions (s+1 and t+1 offsets).  panel_dtype
+    chooses the stored precision of the dual panel layout ("f64", "f32", "bf16", "f16").
+    """
+
+    def __init__(self, A: torch.Tensor, row_offsets: Sequence[int], col_offsets: Sequence[int],
+                 alpha: float, seed: int = 0, panel_dtype: str = "f64"):
+        lib = N.load()
+        if A.dim() != 2 or not A.is_cuda or A.dtype not in (torch.float64, torch.float32):
+            raise ValueError("A must be a 2-D CUDA float64/float32 tensor")
+        if A.stride(1) != 1:
+            raise ValueError("A must be row-major with unit column stride")
+        if panel_dtype not in N.DTYPES:
+            raise ValueError(f"panel_dtype must be one of {sorted(N.DTYPES)}")
+        self.m, self.n = int(A.shape[0]), int(A.shape[1])
+        ro = np.ascontiguousarray(row_offsets, dtype=np.int64)
+        co = np.ascontiguousarray(col_offsets, dtype=np.int64)
+        self.row_offsets, self.col_offsets = ro, co
+        self.s, self.t = len(ro) - 1, len(co) - 1
+        self.alpha, self.seed, self.panel_dtype = float(alpha), int(seed), panel_dtype
+        h = ctypes.c_void_p()
+        a_dt = N.F64_T if A.dtype == torch.float64 else N.F32_T
+        code = lib.rebk_create(ctypes.byref(h), ctypes.c_void_p(A.data_ptr()), a_dt, N.DTYPES[panel_dtype],
+                               self.m, self.n, int(A.stride(0)),
+                               ro.ctypes.data_as(ctypes.c_void_p), self.s,
+                               co.ctypes.data_as(ctypes.c_void_p), self.t,
+                               self.alpha, ctypes.c_uint64(self.seed), _stream_ptr())
+        N.check(code, "rebk_create")
+        self._h = h
+        self.device = A.device
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            N.load().rebk_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------ queries
+    def weights(self):
+        w_row = np.zeros(self.s)
+        w_col = np.zeros(self.t)
+        N.check(N.load().rebk_get_weights(self._h, w_row.ctypes.data_as(ctypes.c_void_p),
+                                          w_col.ctypes.data_as(ctypes.c_void_p)), "rebk_get_weights")
+        return w_row, w_col
+
+    def thresholds(self):
+        T_row = np.zeros(self.s, dtype=np.uint64)
+        T_col = np.zeros(self.t, dtype=np.uint64)
+        N.check(N.load().rebk_get_thresholds(self._h, T_row.ctypes.data_as(ctypes.c_void_p),
+                                             T_col.ctypes.data_as(ctypes.c_void_p)), "rebk_get_thresholds")
+        return T_row, T_col
+
+    def info(self):
+        vals = [ctypes.c_int64() for _ in range(6)]
+        N.check(N.load().rebk_get_info(self._h, *[ctypes.byref(v) for v in vals]), "rebk_get_info")
+        keys = ["m", "n", "s", "t", "max_row_block", "max_col_block"]
+        return {k: v.value for k, v in zip(keys, vals)}
+
+    def sample_blocks(self, k0: int, count: int, system: int = 0):
+        """Device sampler: 0-based (j, i) of iterations k0+1 .. k0+count, as int32 CUDA tensors."""
+        j = torch.empty(count, dtype=torch.int32, device=self.device)
+        i = torch.empty(count, dtype=torch.int32, device=self.device)
+        N.check(N.load().rebk_sample_blocks(self._h, ctypes.c_uint64(system), int(k0), int(count),
+                                            ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(i.data_ptr())),
+                "rebk_sample_blocks")
+        return j, i
+
+    # ------------------------------------------------------------------ solves
+    def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, tol: float = 1e-6,
+              max_iter: int = 100000):
+        """``rebk_solve``: residual stop rule, z^0 = b.  Returns (x, SolveResult)."""
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        res = N.Result()
+        code = N.load().rebk_solve(self._h, _dev_ptr(b, self.m, "b"), _dev_ptr(x0, self.n, "x0"),
+                                   _dev_ptr(x, self.n, "x"), float(tol), int(max_iter), ctypes.byref(res))
+        N.check(code, "rebk_solve")
+        return x, self._result(res)
+
+    def solve_ex(self, b: torch.Tensor, *, x0=None, z0=None, k0: int = 0, max_iter: int = 100000,
+                 x_ref=None, tol: float = 0.0, check_every: int = 0, trace: bool = False,
+                 kernel: str = "auto", grid_wgs: int = 0, x_out=None, z_out=None):
+        """``rebk_solve_ex``.  Returns dict(x, z, result, j, i) (j, i: traces when requested)."""
+        x = x_out if x_out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        z = z_out if z_out is not None else torch.empty(self.m, dtype=torch.float64, device=self.device)
+        tj = ti = None
+        if trace:
+            tj = torch.full((max_iter,), -1, dtype=torch.int32, device=self.device)
+            ti = torch.full((max_iter,), -1, dtype=torch.int32, device=self.device)
+        o = N.SolveOpts()
+        o.b_dev = _dev_ptr(b, self.m, "b")
+        o.x0_dev = _dev_ptr(x0, self.n, "x0")
+        o.z0_dev = _dev_ptr(z0, self.m, "z0")
+        o.k0 = int(k0)
+        o.max_iter = int(max_iter)
+        o.x_ref_dev = _dev_ptr(x_ref, self.n, "x_ref")
+        o.tol = float(tol)
+        o.check_every = int(check_every)
+        o.x_out_dev = _dev_ptr(x, self.n, "x_out")
+        o.z_out_dev = _dev_ptr(z, self.m, "z_out")
+        o.trace_j_dev = _dev_ptr(tj, max_iter, "trace_j", torch.int32)
+        o.trace_i_dev = _dev_ptr(ti, max_iter, "trace_i", torch.int32)
+        o.kernel = N.KERNELS[kernel]
+        o.grid_wgs = int(grid_wgs)
+        res = N.Result()
+        code = N.load().rebk_solve_ex(self._h, ctypes.byref(o), ctypes.byref(res))
+        N.check(code, "rebk_solve_ex")
+        r = self._result(res)
+        out = {"x": x, "z": z, "result": r}
+        if trace:
+            out["j"] = tj[: r.iterations]
+            out["i"] = ti[: r.iterations]
+        return out
+
+    @staticmethod
+    def _result(res: "N.Result") -> SolveResult:
+        return SolveResult(status=N.STATUS_NAMES.get(res.status, str(res.status)), code=int(res.status),
+                           kernel=N.KERNEL_NAMES.get(res.kernel, str(res.kernel)), iterations=int(res.iterations),
+                           rel_err=float(res.rel_err), time_ms=float(res.time_ms))
+
+
+def philox4x64_10(counter: Sequence[int], key: Sequence[int], count: int, device="cuda") -> torch.Tensor:
+    """Device Philox4x64-10 words for counters (c0+q, c1, c2, c3), q < count: uint64 as int64 (count, 4)."""
+    out = torch.empty((count, 4), dtype=torch.int64, device=device)
+    c = [ctypes.c_uint64(int(v)) for v in counter]
+    k = [ctypes.c_uint64(int(v)) for v in key]
+    N.check(N.load().rebk_philox4x64_10(*c, *k, int(count), ctypes.c_void_p(out.data_ptr()), _stream_ptr()),
+            "rebk_philox4x64_10")
+    return out

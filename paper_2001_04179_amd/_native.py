@@ -1,0 +1,96 @@
+"""ctypes declarations of the C ABI in ``include/rebk.h`` (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librebk.so")
+
+P = ctypes.c_void_p
+I32 = ctypes.c_int32
+I64 = ctypes.c_int64
+U64 = ctypes.c_uint64
+F64 = ctypes.c_double
+
+# rebk_dtype_t
+F64_T, F32_T, BF16_T, F16_T = 0, 1, 2, 3
+DTYPES = {"f64": F64_T, "f32": F32_T, "bf16": BF16_T, "f16": F16_T}
+
+# rebk_status_t
+OK, NOT_CONVERGED, DIVERGED = 0, 1, 2
+ERR_INVALID, ERR_HIP, ERR_OOM, ERR_TIMEOUT = -1, -2, -3, -4
+STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "diverged", -1: "invalid", -2: "hip_error", -3: "oom",
+                -4: "timeout"}
+
+# rebk_kernel_t
+KERNELS = {"auto": 0, "workgroup": 1, "grid": 2}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", I32), ("kernel", I32), ("iterations", I64), ("rel_err", F64), ("time_ms", F64)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("b_dev", P), ("x0_dev", P), ("z0_dev", P), ("k0", I64), ("max_iter", I64),
+        ("x_ref_dev", P), ("tol", F64), ("check_every", I64), ("x_out_dev", P), ("z_out_dev", P),
+        ("trace_j_dev", P), ("trace_i_dev", P), ("kernel", I32), ("grid_wgs", I32),
+    ]
+
+
+# name -> (restype, argtypes); every function declared in include/rebk.h
+SIGNATURES = {
+    "rebk_create": (ctypes.c_int, [ctypes.POINTER(P), P, I32, I32, I64, I64, I64, P, I64, P, I64, F64, U64, P]),
+    "rebk_destroy": (None, [P]),
+    "rebk_solve": (ctypes.c_int, [P, P, P, P, F64, I64, ctypes.POINTER(Result)]),
+    "rebk_solve_ex": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Result)]),
+    "rebk_get_weights": (ctypes.c_int, [P, P, P]),
+    "rebk_get_thresholds": (ctypes.c_int, [P, P, P]),
+    "rebk_get_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 6),
+    "rebk_sample_blocks": (ctypes.c_int, [P, U64, I64, I64, P, P]),
+    "rebk_philox4x64_10": (ctypes.c_int, [U64, U64, U64, U64, U64, U64, I64, P, P]),
+    "rebk_last_error": (ctypes.c_char_p, []),
+    "rebk_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class NativeLibraryMissing(RuntimeError):
+    pass
+
+
+def load():
+    """Load ``librebk.so``; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NativeLibraryMissing(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2001_04179_amd.build` "
+            "(the REBK path only runs in the HIP library)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().rebk_last_error().decode()
+
+
+class RebkError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where} failed with {STATUS_NAMES.get(code, code)}: {last_error()}")
+
+
+def check(code: int, where: str) -> int:
+    if code < 0:
+        raise RebkError(code, where)
+    return code

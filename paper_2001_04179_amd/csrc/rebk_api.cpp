@@ -1,0 +1,579 @@
+// Host runtime of librebk.so: argument validation, device memory, sampling tables and the
+// solve drivers behind the C ABI declared in include/rebk.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rebk.h"
+#include "rebk_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(REBK_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t dtype_size(int dt) {
+  switch (dt) {
+    case REBK_F64: return 8;
+    case REBK_F32: return 4;
+    case REBK_BF16: return 2;
+    case REBK_F16: return 2;
+    default: return 0;
+  }
+}
+
+// Cumulative 53-bit thresholds of weights w: T_j = floor(C_j / C_total * 2^53), last = 2^53,
+// with C_j the prefix sums in index order.
+bool build_thresholds(const std::vector<double>& w, std::vector<uint64_t>& T) {
+  const double two53 = 9007199254740992.0;
+  double total = 0.0;
+  for (double x : w) {
+    if (!(x >= 0.0)) return false;
+    total = total + x;
+  }
+  if (!(total > 0.0) || !std::isfinite(total)) return false;
+  T.assign(w.size(), 0);
+  double C = 0.0;
+  for (size_t j = 0; j + 1 < w.size(); ++j) {
+    C = C + w[j];
+    T[j] = (uint64_t)std::floor(C / total * two53);
+  }
+  T.back() = (uint64_t)1 << 53;
+  return true;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct rebk_handle {
+  int64_t m = 0, n = 0, s = 0, t = 0;
+  int32_t max_nI = 0, max_nJ = 0;
+  int panel_dtype = 0;
+  double alpha = 0.0;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cus = 0;
+  double fro2 = 0.0;  // ||A||_F^2 (row-weight total)
+  std::vector<int64_t> row_off, col_off;
+  std::vector<double> w_row, w_col;
+  std::vector<uint64_t> T_row_h, T_col_h;
+  // device memory
+  void* Arow = nullptr;
+  void* Acol = nullptr;
+  int64_t* row_off_d = nullptr;
+  int64_t* col_off_d = nullptr;
+  uint64_t* T_row = nullptr;
+  uint64_t* T_col = nullptr;
+  double* coef_row = nullptr;
+  double* coef_col = nullptr;
+  rebk::DevStatus* status_d = nullptr;
+  double* partials = nullptr;  // residual / error partial sums
+  int nparts = 0;
+  // grid workspace
+  unsigned* bar = nullptr;
+  double* acc = nullptr;
+  int* timeout = nullptr;
+  size_t acc_cap = 0;
+  size_t bar_cap = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  ~rebk_handle() {
+    dfree(Arow);
+    dfree(Acol);
+    dfree(row_off_d);
+    dfree(col_off_d);
+    dfree(T_row);
+    dfree(T_col);
+    dfree(coef_row);
+    dfree(coef_col);
+    dfree(status_d);
+    dfree(partials);
+    dfree(bar);
+    dfree(acc);
+    dfree(timeout);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+int check_offsets(const int64_t* off, int64_t nb, int64_t total, const char* what, int32_t* maxsz) {
+  if (!off) return fail(REBK_ERR_INVALID, "%s offsets are NULL", what);
+  if (nb <= 0 || nb > (1ll << 30)) return fail(REBK_ERR_INVALID, "%s block count %lld out of range", what, (long long)nb);
+  if (off[0] != 0 || off[nb] != total)
+    return fail(REBK_ERR_INVALID, "%s offsets must start at 0 and end at %lld", what, (long long)total);
+  int64_t mx = 0;
+  for (int64_t i = 0; i < nb; ++i) {
+    if (off[i + 1] <= off[i]) return fail(REBK_ERR_INVALID, "%s offsets must be strictly increasing", what);
+    if (off[i + 1] - off[i] > mx) mx = off[i + 1] - off[i];
+  }
+  if (mx > (1 << 20)) return fail(REBK_ERR_INVALID, "%s block of %lld is too large", what, (long long)mx);
+  *maxsz = (int32_t)mx;
+  return REBK_OK;
+}
+
+int ensure_grid_workspace(rebk_handle* h, size_t acc_entries, size_t bar_words) {
+  if (acc_entries > h->acc_cap) {
+    dfree(h->acc);
+    if (hipMalloc((void**)&h->acc, acc_entries * sizeof(double)) != hipSuccess)
+      return fail(REBK_ERR_OOM, "cannot allocate %zu accumulator entries", acc_entries);
+    h->acc_cap = acc_entries;
+  }
+  if (bar_words > h->bar_cap) {
+    dfree(h->bar);
+    if (hipMalloc((void**)&h->bar, bar_words * sizeof(unsigned)) != hipSuccess)
+      return fail(REBK_ERR_OOM, "cannot allocate the barrier words");
+    h->bar_cap = bar_words;
+  }
+  if (!h->timeout && hipMalloc((void**)&h->timeout, sizeof(int)) != hipSuccess)
+    return fail(REBK_ERR_OOM, "cannot allocate the timeout flag");
+  return REBK_OK;
+}
+
+rebk::SolveArgs base_args(const rebk_handle* h) {
+  rebk::SolveArgs a{};
+  a.Arow = h->Arow;
+  a.Acol = h->Acol;
+  a.row_off = h->row_off_d;
+  a.col_off = h->col_off_d;
+  a.T_row = h->T_row;
+  a.T_col = h->T_col;
+  a.coef_row = h->coef_row;
+  a.coef_col = h->coef_col;
+  a.m = h->m;
+  a.n = h->n;
+  a.s = (int32_t)h->s;
+  a.t = (int32_t)h->t;
+  a.max_nI = h->max_nI;
+  a.max_nJ = h->max_nJ;
+  a.seed = h->seed;
+  a.sys = 0;
+  a.status = h->status_d;
+  return a;
+}
+
+// Sum of nparts partial sums copied to the host (fixed order).
+int host_sum(rebk_handle* h, const double* dev, int cnt, double* out) {
+  std::vector<double> buf(cnt);
+  HIP_TRY(hipMemcpyAsync(buf.data(), dev, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double s = 0.0;
+  for (double v : buf) s += v;
+  *out = s;
+  return REBK_OK;
+}
+
+bool wg_fits(const rebk_handle* h, const rebk::SolveArgs& a) {
+  return rebk::wg_solve_lds_bytes(a) <= 150 * 1024;
+}
+
+// One call of the iteration kernel for iterations k0+1 .. k0+iters.
+int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, int* used_kernel) {
+  if (kernel == REBK_KERNEL_AUTO) {
+    // blocks of a few thousand entries or less: the whole solve in one workgroup
+    const double per_iter = (double)h->m * h->max_nJ + (double)h->n * h->max_nI;
+    kernel = (wg_fits(h, a) && per_iter <= 65536.0) ? REBK_KERNEL_WORKGROUP : REBK_KERNEL_GRID;
+  }
+  *used_kernel = kernel;
+  if (kernel == REBK_KERNEL_WORKGROUP) {
+    if (!wg_fits(h, a)) return fail(REBK_ERR_INVALID, "system too large for the one-workgroup kernel");
+    HIP_TRY(rebk::launch_wg_solve(a, h->panel_dtype, rebk::kWgThreads, rebk::wg_solve_lds_bytes(a), h->stream));
+    return REBK_OK;
+  }
+  if (kernel != REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel %d", kernel);
+  int G = grid_wgs > 0 ? grid_wgs : h->cus;
+  const size_t lds = rebk::grid_solve_lds_bytes(a, G, h->panel_dtype);
+  if (lds > 160 * 1024) return fail(REBK_ERR_INVALID, "grid kernel needs %zu bytes of LDS per workgroup", lds);
+  int per_cu = 0;
+  HIP_TRY(rebk::grid_solve_max_blocks(h->panel_dtype, lds, &per_cu));
+  if (per_cu <= 0 || G > per_cu * h->cus)
+    return fail(REBK_ERR_INVALID, "grid of %d workgroups cannot be co-resident (%d per CU)", G, per_cu);
+  if ((h->n + G - 1) / G > rebk::kGridThreads)
+    return fail(REBK_ERR_INVALID, "too many columns per workgroup; use a larger grid");
+  rebk::GridSync gs{};
+  gs.stripes = 4;
+  gs.groups = G < 8 ? G : 8;
+  gs.stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
+  const size_t acc_entries = (size_t)3 * gs.stripes * gs.stride;
+  const size_t bar_words = (size_t)(1 + 2 * gs.groups) * 32;
+  int rc = ensure_grid_workspace(h, acc_entries, bar_words);
+  if (rc != REBK_OK) return rc;
+  gs.acc = h->acc;
+  gs.bar = h->bar;
+  gs.timeout = h->timeout;
+  HIP_TRY(hipMemsetAsync(h->acc, 0, acc_entries * sizeof(double), h->stream));
+  HIP_TRY(hipMemsetAsync(h->bar, 0, bar_words * sizeof(unsigned), h->stream));
+  HIP_TRY(hipMemsetAsync(h->timeout, 0, sizeof(int), h->stream));
+  HIP_TRY(rebk::launch_grid_solve(a, gs, h->panel_dtype, G, h->stream));
+  return REBK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rebk_last_error(void) { return g_err; }
+
+const char* rebk_version(void) { return "rebk-gfx950 0.1"; }
+
+int rebk_create(rebk_handle_t* out, const void* A_dev, int32_t a_dtype, int32_t panel_dtype, int64_t m, int64_t n,
+                int64_t lda, const int64_t* row_offsets, int64_t s, const int64_t* col_offsets, int64_t t,
+                double alpha, uint64_t seed, void* stream) {
+  g_err[0] = 0;
+  if (!out) return fail(REBK_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!A_dev) return fail(REBK_ERR_INVALID, "A is NULL");
+  if (a_dtype != REBK_F64 && a_dtype != REBK_F32) return fail(REBK_ERR_INVALID, "A must be FP64 or FP32");
+  if (dtype_size(panel_dtype) == 0) return fail(REBK_ERR_INVALID, "unknown panel dtype %d", panel_dtype);
+  if (m <= 0 || n <= 0 || lda < n) return fail(REBK_ERR_INVALID, "bad sizes m=%lld n=%lld lda=%lld", (long long)m, (long long)n, (long long)lda);
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(REBK_ERR_INVALID, "alpha must be positive and finite");
+  int32_t max_nI = 0, max_nJ = 0;
+  int rc = check_offsets(row_offsets, s, m, "row", &max_nI);
+  if (rc != REBK_OK) return rc;
+  rc = check_offsets(col_offsets, t, n, "column", &max_nJ);
+  if (rc != REBK_OK) return rc;
+
+  rebk_handle* h = new (std::nothrow) rebk_handle();
+  if (!h) return fail(REBK_ERR_OOM, "host allocation failed");
+  h->m = m;
+  h->n = n;
+  h->s = s;
+  h->t = t;
+  h->max_nI = max_nI;
+  h->max_nJ = max_nJ;
+  h->panel_dtype = panel_dtype;
+  h->alpha = alpha;
+  h->seed = seed;
+  h->stream = (hipStream_t)stream;
+  h->row_off.assign(row_offsets, row_offsets + s + 1);
+  h->col_off.assign(col_offsets, col_offsets + t + 1);
+
+  auto bail = [&](int code) {
+    delete h;
+    return code;
+  };
+#define TRY_H(expr)                                                                           \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return bail(fail(REBK_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+  } while (0)
+#define ALLOC_H(ptr, bytes)                                                                    \
+  do {                                                                                         \
+    if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess)                                      \
+      return bail(fail(REBK_ERR_OOM, "cannot allocate %zu bytes", (size_t)(bytes)));          \
+  } while (0)
+
+  TRY_H(hipGetDevice(&h->device));
+  TRY_H(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device));
+  TRY_H(hipEventCreate(&h->ev0));
+  TRY_H(hipEventCreate(&h->ev1));
+
+  const size_t esz = dtype_size(panel_dtype);
+  const size_t elems = (size_t)m * (size_t)n;
+  ALLOC_H(h->Arow, elems * esz);
+  ALLOC_H(h->Acol, elems * esz);
+  ALLOC_H(h->row_off_d, (s + 1) * sizeof(int64_t));
+  ALLOC_H(h->col_off_d, (t + 1) * sizeof(int64_t));
+  ALLOC_H(h->T_row, s * sizeof(uint64_t));
+  ALLOC_H(h->T_col, t * sizeof(uint64_t));
+  ALLOC_H(h->coef_row, s * sizeof(double));
+  ALLOC_H(h->coef_col, t * sizeof(double));
+  ALLOC_H(h->status_d, sizeof(rebk::DevStatus));
+  h->nparts = 512;
+  ALLOC_H(h->partials, 2 * (size_t)h->nparts * sizeof(double));
+
+  // scratch for packing and the weights
+  std::vector<int32_t> rowblk(m), colblk(n);
+  for (int64_t i = 0; i < s; ++i)
+    for (int64_t r = row_offsets[i]; r < row_offsets[i + 1]; ++r) rowblk[r] = (int32_t)i;
+  for (int64_t j = 0; j < t; ++j)
+    for (int64_t c = col_offsets[j]; c < col_offsets[j + 1]; ++c) colblk[c] = (int32_t)j;
+  int32_t *rowblk_d = nullptr, *colblk_d = nullptr;
+  double *row_sq = nullptr, *colrow_sq = nullptr, *w_d = nullptr;
+  int* bad_d = nullptr;
+  auto free_scratch = [&]() {
+    dfree(rowblk_d);
+    dfree(colblk_d);
+    dfree(row_sq);
+    dfree(colrow_sq);
+    dfree(w_d);
+    dfree(bad_d);
+  };
+  auto bail2 = [&](int code) {
+    free_scratch();
+    return bail(code);
+  };
+#define TRY_S(expr)                                                                             \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return bail2(fail(REBK_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_))); \
+  } while (0)
+#define ALLOC_S(ptr, bytes)                                                                      \
+  do {                                                                                           \
+    if (hipMalloc((void**)&(ptr), (bytes)) != hipSuccess)                                        \
+      return bail2(fail(REBK_ERR_OOM, "cannot allocate %zu bytes", (size_t)(bytes)));           \
+  } while (0)
+
+  ALLOC_S(rowblk_d, m * sizeof(int32_t));
+  ALLOC_S(colblk_d, n * sizeof(int32_t));
+  ALLOC_S(row_sq, m * sizeof(double));
+  ALLOC_S(colrow_sq, (size_t)m * t * sizeof(double));
+  ALLOC_S(w_d, (s + t) * sizeof(double));
+  ALLOC_S(bad_d, sizeof(int));
+  hipStream_t st = h->stream;
+  TRY_S(hipMemcpyAsync(rowblk_d, rowblk.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  TRY_S(hipMemcpyAsync(colblk_d, colblk.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  TRY_S(hipMemcpyAsync(h->row_off_d, h->row_off.data(), (s + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  TRY_S(hipMemcpyAsync(h->col_off_d, h->col_off.data(), (t + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  TRY_S(hipMemsetAsync(bad_d, 0, sizeof(int), st));
+  TRY_S(rebk::launch_finite_check(A_dev, a_dtype, lda, m, n, bad_d, st));
+  TRY_S(rebk::launch_pack(A_dev, a_dtype, lda, panel_dtype, m, n, h->row_off_d, h->col_off_d, rowblk_d, colblk_d,
+                          h->Arow, h->Acol, st));
+  TRY_S(rebk::launch_block_weights(h->Arow, h->Acol, panel_dtype, m, n, h->row_off_d, (int32_t)s, h->col_off_d,
+                                   (int32_t)t, rowblk_d, row_sq, colrow_sq, w_d, w_d + s, st));
+  std::vector<double> w(s + t);
+  int bad = 0;
+  TRY_S(hipMemcpyAsync(w.data(), w_d, (s + t) * sizeof(double), hipMemcpyDeviceToHost, st));
+  TRY_S(hipMemcpyAsync(&bad, bad_d, sizeof(int), hipMemcpyDeviceToHost, st));
+  TRY_S(hipStreamSynchronize(st));
+  free_scratch();
+  if (bad) return bail(fail(REBK_ERR_INVALID, "A has a non-finite entry"));
+  h->w_row.assign(w.begin(), w.begin() + s);
+  h->w_col.assign(w.begin() + s, w.end());
+  if (!build_thresholds(h->w_row, h->T_row_h) || !build_thresholds(h->w_col, h->T_col_h))
+    return bail(fail(REBK_ERR_INVALID, "||A||_F is zero or not finite"));
+  h->fro2 = 0.0;
+  for (double x : h->w_row) h->fro2 += x;
+  std::vector<double> cr(s), cc(t);
+  for (int64_t i = 0; i < s; ++i) cr[i] = h->w_row[i] > 0.0 ? alpha / h->w_row[i] : 0.0;
+  for (int64_t j = 0; j < t; ++j) cc[j] = h->w_col[j] > 0.0 ? alpha / h->w_col[j] : 0.0;
+  TRY_H(hipMemcpyAsync(h->T_row, h->T_row_h.data(), s * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  TRY_H(hipMemcpyAsync(h->T_col, h->T_col_h.data(), t * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  TRY_H(hipMemcpyAsync(h->coef_row, cr.data(), s * sizeof(double), hipMemcpyHostToDevice, st));
+  TRY_H(hipMemcpyAsync(h->coef_col, cc.data(), t * sizeof(double), hipMemcpyHostToDevice, st));
+  TRY_H(hipStreamSynchronize(st));
+  *out = h;
+  return REBK_OK;
+#undef TRY_H
+#undef ALLOC_H
+#undef TRY_S
+#undef ALLOC_S
+}
+
+void rebk_destroy(rebk_handle_t h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+int rebk_get_info(rebk_handle_t h, int64_t* m, int64_t* n, int64_t* s, int64_t* t, int64_t* max_row_block,
+                  int64_t* max_col_block) {
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (m) *m = h->m;
+  if (n) *n = h->n;
+  if (s) *s = h->s;
+  if (t) *t = h->t;
+  if (max_row_block) *max_row_block = h->max_nI;
+  if (max_col_block) *max_col_block = h->max_nJ;
+  return REBK_OK;
+}
+
+int rebk_get_weights(rebk_handle_t h, double* w_row, double* w_col) {
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (w_row) std::memcpy(w_row, h->w_row.data(), h->s * sizeof(double));
+  if (w_col) std::memcpy(w_col, h->w_col.data(), h->t * sizeof(double));
+  return REBK_OK;
+}
+
+int rebk_get_thresholds(rebk_handle_t h, uint64_t* T_row, uint64_t* T_col) {
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (T_row) std::memcpy(T_row, h->T_row_h.data(), h->s * sizeof(uint64_t));
+  if (T_col) std::memcpy(T_col, h->T_col_h.data(), h->t * sizeof(uint64_t));
+  return REBK_OK;
+}
+
+int rebk_sample_blocks(rebk_handle_t h, uint64_t system, int64_t k0, int64_t count, int32_t* j_out_dev,
+                       int32_t* i_out_dev) {
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (count < 0 || k0 < 0 || (count > 0 && (!j_out_dev || !i_out_dev)))
+    return fail(REBK_ERR_INVALID, "bad sampler arguments");
+  if (count == 0) return REBK_OK;
+  HIP_TRY(rebk::launch_sample(h->T_row, (int32_t)h->s, h->T_col, (int32_t)h->t, h->seed, system, k0, count, j_out_dev,
+                              i_out_dev, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return REBK_OK;
+}
+
+int rebk_philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1, int64_t count,
+                       uint64_t* out_dev, void* stream) {
+  if (count < 0 || (count > 0 && !out_dev)) return fail(REBK_ERR_INVALID, "bad Philox arguments");
+  if (count == 0) return REBK_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(rebk::launch_philox(c0, c1, c2, c3, k0, k1, count, out_dev, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return REBK_OK;
+}
+
+int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_result_t* res) {
+  g_err[0] = 0;
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (!o) return fail(REBK_ERR_INVALID, "opts is NULL");
+  if (!o->b_dev || !o->x_out_dev) return fail(REBK_ERR_INVALID, "b and x_out are required");
+  if (o->max_iter <= 0) return fail(REBK_ERR_INVALID, "max_iter must be positive");
+  if (o->k0 < 0) return fail(REBK_ERR_INVALID, "k0 must be non-negative");
+  if (o->check_every < 0) return fail(REBK_ERR_INVALID, "check_every must be non-negative");
+  if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
+  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel");
+  const bool ref_mode = o->x_ref_dev != nullptr;
+  const bool residual_mode = !ref_mode && o->tol > 0.0;
+  rebk::SolveArgs a = base_args(h);
+  a.b = o->b_dev;
+  a.x_in = o->x0_dev;
+  a.z_in = o->z0_dev;
+  a.x_out = o->x_out_dev;
+  a.z_out = o->z_out_dev;
+  a.x_ref = o->x_ref_dev;
+  a.tol = o->tol;
+  a.k0 = o->k0;
+  a.trace_j = o->trace_j_dev;
+  a.trace_i = o->trace_i_dev;
+  if ((a.trace_j == nullptr) != (a.trace_i == nullptr)) return fail(REBK_ERR_INVALID, "give both trace buffers or none");
+
+  if (ref_mode) {
+    double xr2 = 0.0;
+    // ||x_ref||^2, summed on the host from a copy
+    std::vector<double> xr(h->n);
+    HIP_TRY(hipMemcpyAsync(xr.data(), o->x_ref_dev, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (double v : xr) xr2 += v * v;
+    if (!(xr2 > 0.0) || !std::isfinite(xr2)) return fail(REBK_ERR_INVALID, "x_ref must be non-zero and finite");
+    a.xref_sq = xr2;
+  }
+
+  rebk_result_t r{};
+  r.rel_err = -1.0;
+  int used = 0;
+  float ms_total = 0.0f;
+  if (!residual_mode) {
+    a.max_iter = o->max_iter;
+    a.check_every = o->check_every > 0 ? o->check_every : 1;
+    HIP_TRY(hipEventRecord(h->ev0, h->stream));
+    int rc = run_iterations(h, a, o->kernel, o->grid_wgs, &used);
+    if (rc != REBK_OK) return rc;
+    HIP_TRY(hipEventRecord(h->ev1, h->stream));
+    rebk::DevStatus ds{};
+    HIP_TRY(hipMemcpyAsync(&ds, h->status_d, sizeof(ds), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipEventElapsedTime(&ms_total, h->ev0, h->ev1));
+    if (ds.status == REBK_ERR_TIMEOUT) return fail(REBK_ERR_TIMEOUT, "grid barrier spin limit exceeded");
+    r.status = ref_mode ? ds.status : REBK_OK;
+    r.iterations = ds.last_k - o->k0;
+    if (ref_mode && ds.err2 >= 0.0) r.rel_err = std::sqrt(ds.err2) / std::sqrt(a.xref_sq);
+  } else {
+    // residual stop rule: chunks of check_every iterations, norms of b - z - A x and A^T z between chunks
+    const int64_t ce = o->check_every > 0 ? o->check_every : 256;
+    const bool have_z_out = o->z_out_dev != nullptr;
+    double* zbuf = o->z_out_dev;
+    if (!have_z_out && hipMalloc((void**)&zbuf, h->m * sizeof(double)) != hipSuccess)
+      return fail(REBK_ERR_OOM, "cannot allocate z");
+    double bnorm2 = 0.0;
+    {
+      std::vector<double> bh(h->m);
+      hipError_t e = hipMemcpyAsync(bh.data(), o->b_dev, h->m * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) {
+        if (!have_z_out) (void)hipFree(zbuf);
+        return fail(REBK_ERR_HIP, "copy of b: %s", hipGetErrorString(e));
+      }
+      for (double v : bh) bnorm2 += v * v;
+    }
+    const double bnorm = std::sqrt(bnorm2), anorm = std::sqrt(h->fro2);
+    int64_t done = 0;
+    int status = REBK_NOT_CONVERGED;
+    int rc = REBK_OK;
+    while (done < o->max_iter) {
+      const int64_t chunk = (o->max_iter - done) < ce ? (o->max_iter - done) : ce;
+      rebk::SolveArgs c = a;
+      c.k0 = o->k0 + done;
+      c.max_iter = chunk;
+      c.check_every = chunk;
+      c.x_in = done == 0 ? o->x0_dev : o->x_out_dev;
+      c.z_in = done == 0 ? o->z0_dev : zbuf;
+      c.z_out = zbuf;
+      c.x_ref = nullptr;
+      c.tol = 0.0;
+      c.trace_j = o->trace_j_dev ? o->trace_j_dev + done : nullptr;
+      c.trace_i = o->trace_i_dev ? o->trace_i_dev + done : nullptr;
+      float ms = 0.0f;
+      if (hipEventRecord(h->ev0, h->stream) != hipSuccess) { rc = fail(REBK_ERR_HIP, "event record failed"); break; }
+      rc = run_iterations(h, c, o->kernel, o->grid_wgs, &used);
+      if (rc != REBK_OK) break;
+      if (hipEventRecord(h->ev1, h->stream) != hipSuccess) { rc = fail(REBK_ERR_HIP, "event record failed"); break; }
+      done += chunk;
+      hipError_t e = rebk::launch_residual(h->Arow, h->Acol, h->panel_dtype, c, o->x_out_dev, zbuf, h->partials,
+                                           h->nparts, h->stream);
+      if (e != hipSuccess) { rc = fail(REBK_ERR_HIP, "residual kernel: %s", hipGetErrorString(e)); break; }
+      std::vector<double> parts(2 * h->nparts);
+      e = hipMemcpyAsync(parts.data(), h->partials, parts.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev0, h->ev1);
+      if (e != hipSuccess) { rc = fail(REBK_ERR_HIP, "residual readback: %s", hipGetErrorString(e)); break; }
+      ms_total += ms;
+      double f2 = 0.0, g2 = 0.0;
+      for (int q = 0; q < h->nparts; ++q) f2 += parts[q];
+      for (int q = 0; q < h->nparts; ++q) g2 += parts[h->nparts + q];
+      const double rf = std::sqrt(f2) / (bnorm > 0 ? bnorm : 1.0);
+      const double rg = std::sqrt(g2) / ((anorm * bnorm) > 0 ? anorm * bnorm : 1.0);
+      r.rel_err = rf > rg ? rf : rg;
+      if (!std::isfinite(f2) || !std::isfinite(g2) || r.rel_err > 1e6) { status = REBK_DIVERGED; break; }
+      if (rf <= o->tol && rg <= o->tol) { status = REBK_OK; break; }
+    }
+    if (!have_z_out) (void)hipFree(zbuf);
+    if (rc != REBK_OK) return rc;
+    r.status = status;
+    r.iterations = done;
+  }
+  r.kernel = used;
+  r.time_ms = ms_total;
+  if (res) *res = r;
+  return r.status;
+}
+
+int rebk_solve(rebk_handle_t h, const double* b_dev, const double* x0_dev, double* x_out_dev, double tol,
+               int64_t max_iter, rebk_result_t* res) {
+  rebk_solve_opts_t o{};
+  o.b_dev = b_dev;
+  o.x0_dev = x0_dev;
+  o.max_iter = max_iter;
+  o.tol = tol;
+  o.x_out_dev = x_out_dev;
+  o.kernel = REBK_KERNEL_AUTO;
+  return rebk_solve_ex(h, &o, res);
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal declarations shared by the library's translation units (kernels and host API).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rebk {
+
+// Device-side status block written by the solve kernels.
+struct DevStatus {
+  int32_t status;      // rebk_status_t of the device loop
+  int32_t stopped;     // 1 if the stop rule fired
+  int64_t last_k;      // absolute iteration index of the returned x (k0 + iterations)
+  double err2;         // ||x - x_ref||^2 at the last check (or -1)
+  int64_t check_k;     // iteration of that check
+};
+
+// Everything a solve kernel needs; device pointers unless noted.
+struct SolveArgs {
+  const void* Arow;          // row panels: block i is an n x nI_i column-major panel at n*row_off[i]
+  const void* Acol;          // column panels: block j is an m x nJ_j row-major panel at m*col_off[j]
+  const int64_t* row_off;    // s+1
+  const int64_t* col_off;    // t+1
+  const uint64_t* T_row;     // s cumulative 53-bit thresholds
+  const uint64_t* T_col;     // t cumulative 53-bit thresholds
+  const double* coef_row;    // alpha / ||A_{I_i,:}||_F^2
+  const double* coef_col;    // alpha / ||A_{:,J_j}||_F^2
+  int64_t m, n;
+  int32_t s, t;
+  int32_t max_nI, max_nJ;
+  uint64_t seed, sys;
+  const double* b;
+  const double* x_in;        // NULL: x0 = 0
+  const double* z_in;        // NULL: z0 = b
+  double* x_out;
+  double* z_out;             // may be NULL
+  const double* x_ref;       // NULL: no reference error
+  double xref_sq;            // ||x_ref||^2 (host-computed)
+  double tol;                // relative tolerance (<= 0: none)
+  int64_t k0;
+  int64_t max_iter;
+  int64_t check_every;
+  int32_t* trace_j;
+  int32_t* trace_i;
+  DevStatus* status;
+};
+
+// Synchronisation workspace of the persistent grid kernel.
+struct GridSync {
+  unsigned* bar;      // counters and release flags, zeroed before every launch
+  double* acc;        // 3 x stripes x stride accumulators, zeroed before every launch
+  int* timeout;       // set when a barrier exceeded its spin limit
+  int32_t stripes;
+  int32_t stride;     // entries per stripe (>= max_nJ + max_nI + 1)
+  int32_t groups;     // first-level barrier groups
+};
+
+// Launchers (defined in rebk_kernels.hip).  All return hipError_t.
+hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype, int64_t m, int64_t n,
+                       const int64_t* row_off_d, const int64_t* col_off_d, const int32_t* rowblk_d,
+                       const int32_t* colblk_d, void* Arow, void* Acol, hipStream_t st);
+hipError_t launch_finite_check(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n, int* bad,
+                               hipStream_t st);
+hipError_t launch_block_weights(const void* Arow, const void* Acol, int panel_dtype, int64_t m, int64_t n,
+                                const int64_t* row_off_d, int32_t s, const int64_t* col_off_d, int32_t t,
+                                const int32_t* rowblk_d, double* row_sq, double* colrow_sq, double* w_row,
+                                double* w_col, hipStream_t st);
+hipError_t launch_sample(const uint64_t* T_row, int32_t s, const uint64_t* T_col, int32_t t, uint64_t seed,
+                         uint64_t sys, int64_t k0, int64_t count, int32_t* j_out, int32_t* i_out,
+                         hipStream_t st);
+hipError_t launch_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                         int64_t count, uint64_t* out, hipStream_t st);
+hipError_t launch_wg_solve(const SolveArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st);
+size_t wg_solve_lds_bytes(const SolveArgs& a);
+hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_dtype, int grid, hipStream_t st);
+size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype);
+hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, const SolveArgs& a,
+                           const double* x, const double* z, double* partials, int nparts, hipStream_t st);
+hipError_t launch_err2(const double* x, const double* x_ref, int64_t n, double* partials, int nparts,
+                       hipStream_t st);
+
+constexpr int kGridThreads = 256;
+constexpr int kWgThreads = 256;
+
+}  // namespace rebk

@@ -1,0 +1,68 @@
+"""The C ABI without a GPU: the library loads, exports every function include/rebk.h declares,
+and host-side argument validation answers before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rebk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rebk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_interface():
+    names = declared_functions()
+    for required in ("rebk_create", "rebk_solve", "rebk_solve_ex", "rebk_destroy", "rebk_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2001_04179_amd import _native
+    lib = _native.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_native.SIGNATURES)
+
+
+def test_version_and_error_strings():
+    from paper_2001_04179_amd import _native
+    lib = _native.load()
+    assert lib.rebk_version().decode().startswith("rebk")
+    assert isinstance(lib.rebk_last_error(), bytes)
+
+
+def test_host_validation_without_device():
+    from paper_2001_04179_amd import _native as N
+    lib = N.load()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ro = (ctypes.c_int64 * 3)(0, 5, 10)
+    co = (ctypes.c_int64 * 2)(0, 4)
+    bad_ro = (ctypes.c_int64 * 3)(0, 7, 5)
+    # NULL A
+    assert lib.rebk_create(ctypes.byref(h), None, 0, 0, 10, 4, 4, ro, 2, co, 1, 1.0, 0, None) == N.ERR_INVALID
+    # non-increasing offsets
+    assert lib.rebk_create(ctypes.byref(h), fake, 0, 0, 10, 4, 4, bad_ro, 2, co, 1, 1.0, 0, None) == N.ERR_INVALID
+    assert "increasing" in lib.rebk_last_error().decode() or "end at" in lib.rebk_last_error().decode()
+    # alpha <= 0, unknown dtype, lda < n
+    assert lib.rebk_create(ctypes.byref(h), fake, 0, 0, 10, 4, 4, ro, 2, co, 1, 0.0, 0, None) == N.ERR_INVALID
+    assert lib.rebk_create(ctypes.byref(h), fake, 0, 9, 10, 4, 4, ro, 2, co, 1, 1.0, 0, None) == N.ERR_INVALID
+    assert lib.rebk_create(ctypes.byref(h), fake, 0, 0, 10, 4, 3, ro, 2, co, 1, 1.0, 0, None) == N.ERR_INVALID
+    assert lib.rebk_create(ctypes.byref(h), fake, 2, 0, 10, 4, 4, ro, 2, co, 1, 1.0, 0, None) == N.ERR_INVALID
+    # NULL handle everywhere
+    assert lib.rebk_solve_ex(None, None, None) == N.ERR_INVALID
+    assert lib.rebk_get_weights(None, None, None) == N.ERR_INVALID
+    lib.rebk_destroy(None)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_2001_04179_amd import _native
+    monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(_native.NativeLibraryMissing):
+        _native.load()

@@ -1,0 +1,229 @@
+"""GPU <-> oracle parity through the C ABI: block sequences bit for bit, iterates to 1e-10.
+
+Every case runs the HIP library (``librebk.so``) and replays the same iterations in the FP64 CPU
+oracle.  Sizes span several workgroup tiles with ragged last blocks; the degenerate partitions of
+the method (one block, single rows and columns) and over/underdetermined, rank-deficient and
+consistent systems are covered.
+"""
+import numpy as np
+import pytest
+
+from paper_2001_04179_amd import workloads as W
+from tests._helpers import gpu_vs_oracle, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ["workgroup", "grid"]
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return W.dense_gaussian_1000x100()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_dense_1000x100_to_1e6(rebk, oracle_lib, cfg1, kernel):
+    S = cfg1
+    print(f"case dense 1000x100 kernel={kernel}", flush=True)
+    out, ref = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=5000, tol=1e-6)
+    r = out["result"]
+    assert r.status == "ok" and r.kernel == kernel
+    # the oracle, checking every iteration, stops at the same iteration
+    stop = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=5000,
+                                 x_ref=S.x_ref, tol=1e-6, trace=False)
+    assert stop["iterations"] == r.iterations
+    assert rel(out["x"].cpu().numpy(), S.x_ref) < 1e-6
+    assert abs(r.rel_err - stop["err"]) <= 1e-9 * max(stop["err"], 1e-300) + 1e-15
+
+
+@pytest.mark.parametrize("grid_wgs", [2, 7, 9, 64, 256, 512, 1000])
+def test_grid_sizes(rebk, oracle_lib, cfg1, grid_wgs):
+    """Grids smaller than the barrier's group count, odd sizes, and more workgroups than rows
+    or columns (workgroups that own nothing still take part in every reduction)."""
+    print(f"case dense 1000x100 grid_wgs={grid_wgs}", flush=True)
+    gpu_vs_oracle(rebk, oracle_lib, cfg1, kernel="grid", grid_wgs=grid_wgs, max_iter=300)
+
+
+def test_grid_too_small_is_rejected(rebk, cfg1):
+    """One workgroup cannot hold the whole 1000 x 100 iterate plus its slabs in LDS."""
+    S = cfg1
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    with pytest.raises(rebk.RebkError, match="invalid"):
+        solver.solve_ex(to_dev(S.b), max_iter=10, kernel="grid", grid_wgs=1)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_ragged_blocks(rebk, oracle_lib, kernel):
+    S = W.type2(517, 203, rng_seed=7, noise=0.3, row_tau=50, col_tau=16, alpha_c=1.0, seed=99)
+    print(f"case ragged 517x203 kernel={kernel}", flush=True)
+    gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=1500, tol=1e-8)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_underdetermined_rank_deficient(rebk, oracle_lib, kernel):
+    S = W.factor_product(120, 300, 60, rng_seed=3, noise=0.2, row_tau=16, col_tau=32, alpha_c=1.0, seed=5)
+    print(f"case underdetermined 120x300 rank 60 kernel={kernel}", flush=True)
+    out, _ = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=20000, tol=1e-8)
+    assert out["result"].status == "ok"
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rek_special_case(rebk, oracle_lib, kernel):
+    """s = m, t = n, alpha = 1 is the randomized extended Kaczmarz method (Section 2)."""
+    A = np.random.default_rng(11).standard_normal((60, 25))
+    S = W.general(A, rng_seed=12, noise=0.5, row_tau=1, col_tau=1, seed=3)
+    S.alpha = 1.0
+    print(f"case REK 60x25 kernel={kernel}", flush=True)
+    gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=3000)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_single_blocks(rebk, oracle_lib, kernel):
+    """s = t = 1: the sampler always draws the whole matrix."""
+    A = np.random.default_rng(13).standard_normal((90, 40))
+    S = W.general(A, rng_seed=14, noise=0.2, row_off=[0, 90], col_off=[0, 40], seed=8)
+    print(f"case one block 90x40 kernel={kernel}", flush=True)
+    out, ref = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=200)
+    assert np.all(ref["j"] == 0) and np.all(ref["i"] == 0)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_start_and_resume(rebk, oracle_lib, kernel):
+    """x0 != 0, z0 = 0 (then z stays 0: the averaged block Kaczmarz update), and exact resume at k0."""
+    S = W.type2(300, 80, rng_seed=21, noise=0.0, row_tau=30, col_tau=8, seed=4)
+    x0 = np.random.default_rng(22).standard_normal(80)
+    z0 = np.zeros(300)
+    print(f"case x0/z0=0 kernel={kernel}", flush=True)
+    out, ref = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=400, x0=x0, z0=z0)
+    assert np.all(out["z"].cpu().numpy() == 0.0)
+    # resume: 150 + 250 iterations equal 400 iterations of one run
+    first, _ = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=150)
+    x1 = first["x"].cpu().numpy()
+    z1 = first["z"].cpu().numpy()
+    second, _ = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=250, x0=x1, z0=z1, k0=150)
+    whole = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=400)
+    assert np.array_equal(np.concatenate([first["j"].cpu().numpy(), second["j"].cpu().numpy()]), whole["j"])
+    assert rel(second["x"].cpu().numpy(), whole["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("panel", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_low_precision_panels(rebk, oracle_lib, panel, kernel):
+    """Panels stored in FP32/BF16/FP16 with FP64 iterates: the oracle runs in FP64 on the stored
+    values, so the two agree to FP64 rounding."""
+    S = W.type2(400, 120, rng_seed=31, noise=0.1, row_tau=40, col_tau=12, seed=6)
+    rnd = {"f32": W.round_to_f32, "bf16": W.round_to_bf16, "f16": W.round_to_f16}[panel]
+    A_stored = rnd(S.A)
+    print(f"case panels={panel} kernel={kernel}", flush=True)
+    solver = rebk.Solver(to_dev(A_stored), S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
+    w_row, w_col = solver.weights()
+    o_row, o_col = oracle_lib.block_weights(A_stored, S.row_off, S.col_off)
+    assert np.array_equal(w_row, o_row) and np.array_equal(w_col, o_col)
+    solver.close()
+    gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=600, panel=panel, A_stored=A_stored)
+
+
+def test_weights_and_thresholds_bit_equal(rebk, oracle_lib, cfg1):
+    S = cfg1
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    w_row, w_col = solver.weights()
+    o_row, o_col = oracle_lib.block_weights(S.A, S.row_off, S.col_off)
+    assert np.array_equal(w_row, o_row)
+    assert np.array_equal(w_col, o_col)
+    T_row, T_col = solver.thresholds()
+    assert np.array_equal(T_row, oracle_lib.thresholds(o_row))
+    assert np.array_equal(T_col, oracle_lib.thresholds(o_col))
+    info = solver.info()
+    assert info == {"m": 1000, "n": 100, "s": 10, "t": 10, "max_row_block": 100, "max_col_block": 10}
+
+
+@pytest.mark.parametrize("system", [0, 1, 12345])
+def test_sampler_bit_exact(rebk, oracle_lib, cfg1, system):
+    S = cfg1
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, seed=0xDEADBEEF12345)
+    w_row, w_col = oracle_lib.block_weights(S.A, S.row_off, S.col_off)
+    count, k0 = 200000, 987654321
+    j, i = solver.sample_blocks(k0, count, system)
+    oj, oi = oracle_lib.sample_blocks(w_row, w_col, 0xDEADBEEF12345, k0, count, sys=system)
+    assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(i.cpu().numpy(), oi)
+
+
+def test_device_philox_matches_oracle_and_numpy(rebk, oracle_lib):
+    count = 1 << 20
+    for ctr, key in [((0, 0, 0, 0), (0, 0)), ((2**64 - 5, 7, 2**63, 1), (0x243F6A8885A308D3, 0x13198A2E03707344))]:
+        dev = rebk.philox4x64_10(ctr, key, count).cpu().numpy().view(np.uint64)
+        ref = oracle_lib.philox_fill(ctr, key, count)
+        assert np.array_equal(dev, ref)
+    # against NumPy's Philox4x64-10 (its generator advances the counter before each block)
+    bg = np.random.Philox(counter=np.array([41, 3, 0, 0], dtype=np.uint64), key=np.array([99, 5], dtype=np.uint64))
+    words = bg.random_raw(4 * 1000).reshape(1000, 4)
+    dev = rebk.philox4x64_10((42, 3, 0, 0), (99, 5), 1000).cpu().numpy().view(np.uint64)
+    assert np.array_equal(dev, words)
+
+
+def test_residual_stop_rule(rebk, oracle_lib, cfg1):
+    """rebk_solve: no reference solution, stop on ||b - z - A x|| and ||A^T z||."""
+    S = cfg1
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    x, r = solver.solve(to_dev(S.b), tol=1e-10, max_iter=20000)
+    assert r.status == "ok" and r.iterations % 256 == 0
+    ref = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=r.iterations)
+    assert rel(x.cpu().numpy(), ref["x"]) <= 1e-10
+    assert rel(x.cpu().numpy(), S.x_ref) < 1e-8
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_divergence_reported(rebk, cfg1, kernel):
+    S = cfg1
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, 40.0 / max(S.beta_row, S.beta_col), S.seed)
+    out = solver.solve_ex(to_dev(S.b), max_iter=20000, x_ref=to_dev(S.x_ref), tol=1e-6, kernel=kernel)
+    assert out["result"].status == "diverged"
+
+
+def test_invalid_arguments(rebk, cfg1):
+    S = cfg1
+    A = to_dev(S.A)
+    with pytest.raises(rebk.RebkError, match="invalid"):
+        rebk.Solver(A, [0, 500, 400, 1000], S.col_off, 1.0)
+    with pytest.raises(rebk.RebkError, match="invalid"):
+        rebk.Solver(A, S.row_off, S.col_off, -1.0)
+    Abad = A.clone()
+    Abad[3, 4] = float("nan")
+    with pytest.raises(rebk.RebkError, match="invalid"):
+        rebk.Solver(Abad, S.row_off, S.col_off, 1.0)
+    with pytest.raises(rebk.RebkError, match="invalid"):
+        rebk.Solver(A * 0.0, S.row_off, S.col_off, 1.0)
+    solver = rebk.Solver(A, S.row_off, S.col_off, 1.0)
+    with pytest.raises(rebk.RebkError, match="invalid"):
+        solver.solve_ex(to_dev(S.b), max_iter=0)
+
+
+# ------------------------------------------------------------------ the 20000 x 2000 workload
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return W.rank1500_20000x2000()
+
+
+def test_rank1500_20000x2000_prefix(rebk, oracle_lib, cfg2):
+    """Full size, the launch configuration of the benchmark: 300 iterations against the oracle."""
+    print("case 20000x2000 prefix", flush=True)
+    gpu_vs_oracle(rebk, oracle_lib, cfg2, kernel="grid", max_iter=300)
+
+
+@pytest.mark.parametrize("panel", ["f64", "f32"])
+def test_rank1500_20000x2000_converges(rebk, oracle_lib, cfg2, panel):
+    """Full run to relative error 1e-6 against A^+ b; the whole block sequence is the oracle's."""
+    S = cfg2
+    print(f"case 20000x2000 full solve panels={panel}", flush=True)
+    A_stored = S.A if panel == "f64" else W.round_to_f32(S.A)
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
+    out = solver.solve_ex(to_dev(S.b), max_iter=400000, x_ref=to_dev(S.x_ref), tol=1e-6, check_every=1,
+                          trace=True, kernel="grid")
+    r = out["result"]
+    assert r.status == "ok", r
+    assert rel(out["x"].cpu().numpy(), S.x_ref) < 1e-6
+    w_row, w_col = oracle_lib.block_weights(A_stored, S.row_off, S.col_off)
+    oj, oi = oracle_lib.sample_blocks(w_row, w_col, S.seed, 0, r.iterations)
+    assert np.array_equal(out["j"].cpu().numpy(), oj) and np.array_equal(out["i"].cpu().numpy(), oi)
+    print(f"  iterations={r.iterations} time_ms={r.time_ms:.1f}", flush=True)
