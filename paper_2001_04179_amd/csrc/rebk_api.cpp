@@ -94,11 +94,11 @@ struct rebk_handle {
   double* partials = nullptr;  // residual / error partial sums
   int nparts = 0;
   // grid workspace
-  unsigned* bar = nullptr;
-  double* acc = nullptr;
+  unsigned long long* part = nullptr;
+  unsigned long long* gsum = nullptr;
   int* timeout = nullptr;
-  size_t acc_cap = 0;
-  size_t bar_cap = 0;
+  size_t part_cap = 0;
+  size_t gsum_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   ~rebk_handle() {
@@ -112,8 +112,8 @@ struct rebk_handle {
     dfree(coef_col);
     dfree(status_d);
     dfree(partials);
-    dfree(bar);
-    dfree(acc);
+    dfree(part);
+    dfree(gsum);
     dfree(timeout);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -137,18 +137,18 @@ int check_offsets(const int64_t* off, int64_t nb, int64_t total, const char* wha
   return REBK_OK;
 }
 
-int ensure_grid_workspace(rebk_handle* h, size_t acc_entries, size_t bar_words) {
-  if (acc_entries > h->acc_cap) {
-    dfree(h->acc);
-    if (hipMalloc((void**)&h->acc, acc_entries * sizeof(double)) != hipSuccess)
-      return fail(REBK_ERR_OOM, "cannot allocate %zu accumulator entries", acc_entries);
-    h->acc_cap = acc_entries;
+int ensure_grid_workspace(rebk_handle* h, size_t part_words, size_t gsum_words) {
+  if (part_words > h->part_cap) {
+    dfree(h->part);
+    if (hipMalloc((void**)&h->part, part_words * sizeof(unsigned long long)) != hipSuccess)
+      return fail(REBK_ERR_OOM, "cannot allocate %zu partial-sum words", part_words);
+    h->part_cap = part_words;
   }
-  if (bar_words > h->bar_cap) {
-    dfree(h->bar);
-    if (hipMalloc((void**)&h->bar, bar_words * sizeof(unsigned)) != hipSuccess)
-      return fail(REBK_ERR_OOM, "cannot allocate the barrier words");
-    h->bar_cap = bar_words;
+  if (gsum_words > h->gsum_cap) {
+    dfree(h->gsum);
+    if (hipMalloc((void**)&h->gsum, gsum_words * sizeof(unsigned long long)) != hipSuccess)
+      return fail(REBK_ERR_OOM, "cannot allocate %zu group-sum words", gsum_words);
+    h->gsum_cap = gsum_words;
   }
   if (!h->timeout && hipMalloc((void**)&h->timeout, sizeof(int)) != hipSuccess)
     return fail(REBK_ERR_OOM, "cannot allocate the timeout flag");
@@ -215,19 +215,22 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
     return fail(REBK_ERR_INVALID, "grid of %d workgroups cannot be co-resident (%d per CU)", G, per_cu);
   if ((h->n + G - 1) / G > rebk::kGridThreads)
     return fail(REBK_ERR_INVALID, "too many columns per workgroup; use a larger grid");
+  if (h->max_nJ > rebk::kGridThreads)
+    return fail(REBK_ERR_INVALID, "column blocks wider than %d columns need the one-workgroup kernel", rebk::kGridThreads);
   rebk::GridSync gs{};
-  gs.stripes = 4;
-  gs.groups = G < 8 ? G : 8;
+  gs.groups = G < 16 ? G : 16;
+  if (G > 64 * gs.groups) return fail(REBK_ERR_INVALID, "at most %d workgroups in the grid kernel", 64 * gs.groups);
   gs.stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
-  const size_t acc_entries = (size_t)3 * gs.stripes * gs.stride;
-  const size_t bar_words = (size_t)(1 + 2 * gs.groups) * 32;
-  int rc = ensure_grid_workspace(h, acc_entries, bar_words);
+  const size_t part_words = (size_t)2 * G * gs.stride * 2;
+  const size_t gsum_words = (size_t)32 * gs.groups * gs.stride * 2;  // ring of 32 epochs
+  int rc = ensure_grid_workspace(h, part_words, gsum_words);
   if (rc != REBK_OK) return rc;
-  gs.acc = h->acc;
-  gs.bar = h->bar;
+  gs.part = h->part;
+  gs.gsum = h->gsum;
   gs.timeout = h->timeout;
-  HIP_TRY(hipMemsetAsync(h->acc, 0, acc_entries * sizeof(double), h->stream));
-  HIP_TRY(hipMemsetAsync(h->bar, 0, bar_words * sizeof(unsigned), h->stream));
+  // epochs restart at 1 every launch: clear every tag of the previous launch
+  HIP_TRY(hipMemsetAsync(h->part, 0, part_words * sizeof(unsigned long long), h->stream));
+  HIP_TRY(hipMemsetAsync(h->gsum, 0, gsum_words * sizeof(unsigned long long), h->stream));
   HIP_TRY(hipMemsetAsync(h->timeout, 0, sizeof(int), h->stream));
   HIP_TRY(rebk::launch_grid_solve(a, gs, h->panel_dtype, G, h->stream));
   return REBK_OK;

@@ -1,0 +1,588 @@
+// Persistent cooperative REBK kernel for gfx950 (Du, Si, Sun, arXiv:2001.04179, Algorithm 1).
+//
+// Ownership: workgroup w owns rows [w*m/G, (w+1)*m/G) of z and columns [w*n/G, (w+1)*n/G) of x;
+// both stay in LDS for the whole launch.  One grid-wide reduction per iteration carries
+//   - the partial sums of v^{k+1} = A_{:,J_{k+1}}^T z^k over owned rows,
+//   - the partial sums of u^k = A_{I_k,:} x^{k-1} - b_{I_k} + z^k_{I_k} (owned columns, plus
+//     z - b on owned rows), and
+//   - the partial error ||x^{k-1} - x_ref||^2 over owned columns.
+// The z-chain never reads x, so running the x-chain one iteration behind the z-chain is exact and
+// needs a single synchronisation per iteration.
+//
+// The reduction is a deterministic two-level tree merged into the grid barrier: each workgroup
+// stores its partial vector; the last arrival of each group of workgroups (group g holds
+// workgroups g, g+NG, g+2NG, ...) sums its group in member order and stores the group sum; the
+// last group to arrive releases everyone; every workgroup then sums the NG group sums in group
+// order.  All workgroups therefore see bit-identical reduced vectors, and a run is reproducible
+// bit for bit.
+//
+// All cross-workgroup traffic uses device-scope atomic loads and stores (coherent across the
+// eight XCDs without cache-maintenance fences); a workgroup waits for its stores to complete
+// (s_waitcnt vmcnt(0)) before it arrives.  An agent-scope release fence would write back the
+// XCD's L2 and costs microseconds per workgroup on gfx950.
+//
+// Panel slabs: the column slab A_{R_w, J} (owned rows, row-major, contiguous in the column panel)
+// and the row slab A_{I, C_w} (owned columns, column-major, contiguous in the row panel) are read
+// from HBM once each: for the partial sums of one round and, from LDS, for the update of the
+// next.  Because the block sequence depends only on the counter-based generator, the slabs of
+// the next round are loaded into registers while the barrier spins and land in LDS right after.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rebk_device.h"
+#include "rebk_internal.h"
+
+namespace rebk {
+namespace {
+
+using namespace dev;
+
+constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
+constexpr int kSumRing = 32;                // group-sum buffers, one per epoch modulo the ring
+
+__device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Workgroup-scope load: served by the caches, so it may return an out-of-date value; used only
+// for epoch-tagged data, whose tag exposes an out-of-date value.
+__device__ __forceinline__ unsigned long long ld_u64_cached(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void st_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A value published for one epoch: two 64-bit atomic words, each carrying the 32-bit epoch next
+// to one half of the FP64 bit pattern.  A reader accepts the pair only when both words carry the
+// epoch it waits for, so it never takes a stale value or a pair torn between two epochs; no fence
+// or counter is needed to order the data with its arrival.
+__device__ __forceinline__ void st_tagged(unsigned long long* p, double v, unsigned epoch) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  st_u64(p, ((unsigned long long)epoch << 32) | (bits >> 32));
+  st_u64(p + 1, (bits << 32) | (unsigned long long)epoch);
+}
+__device__ __forceinline__ bool tag_ok(unsigned long long w0, unsigned long long w1, unsigned epoch) {
+  return (unsigned)(w0 >> 32) == epoch && (unsigned)w1 == epoch;
+}
+__device__ __forceinline__ double tag_value(unsigned long long w0, unsigned long long w1) {
+  return __longlong_as_double((long long)((w0 << 32) | (w1 >> 32)));
+}
+
+// Wait until every memory operation this wave issued has completed (including copies into LDS);
+// the memory clobber keeps the compiler from moving accesses across.
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+struct GridLayout {
+  int NR, NC;     // max rows / columns owned by one workgroup
+  size_t dbl;     // doubles before the panel slabs
+  size_t slabC;   // panel elements of one column-slab buffer
+  size_t slabR;   // panel elements of one row-slab buffer
+};
+
+__host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int max_nI, int max_nJ, int G, int threads) {
+  GridLayout L;
+  L.NR = (int)((m + G - 1) / G);
+  L.NC = (int)((n + G - 1) / G);
+  L.dbl = 3 * (size_t)L.NR + 2 * (size_t)L.NC + (size_t)max_nJ + (size_t)max_nI + (size_t)threads + 8;
+  L.slabC = (size_t)L.NR * max_nJ;
+  L.slabR = (size_t)L.NC * max_nI;
+  return L;
+}
+
+// Largest power of two <= x, clamped to [1, 64] (lanes that cooperate on one dot product).
+__device__ __forceinline__ int lanes_per_item(int threads, int items) {
+  int q = items > 0 ? threads / items : threads;
+  int p = 1;
+  while (p * 2 <= q && p < 64) p *= 2;
+  return p;
+}
+
+// Sum over aligned groups of `width` lanes (width a power of two <= 64); every lane gets the sum.
+__device__ __forceinline__ double group_sum(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+constexpr int kRing = 128;  // block draws kept ahead (relative iteration q in slot (q - 1) & 127)
+
+// Bytes of a panel range that go through the LDS copy path: the 4-byte-aligned whole-dword
+// prefix (0 if the start is not 4-byte aligned).
+template <typename TP>
+__device__ __forceinline__ int dma_bytes(const TP* src, int elems) {
+  if (src == nullptr || (reinterpret_cast<uintptr_t>(src) & 3u) != 0) return 0;
+  return (int)((elems * sizeof(TP)) & ~(size_t)3);
+}
+
+// Waves 1..3 copy nbytes (a multiple of 4) from global memory into LDS with global_load_lds
+// (asynchronous, no registers): one dword per lane, 256 bytes per wave instruction.  The copy is
+// complete for the issuing wave after s_waitcnt vmcnt(0).
+__device__ __forceinline__ void dma_to_lds(const void* src, void* dst, int nbytes) {
+  const int wave = (int)(threadIdx.x >> 6) - 1, lane = (int)(threadIdx.x & 63);
+  const int nchunks = (nbytes + 255) >> 8;
+  const char* s = (const char*)src;
+  char* d = (char*)dst;
+  for (int ch = wave; ch < nchunks; ch += 3) {
+    const int off = ch * 256 + lane * 4;
+    if (off < nbytes)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off),
+                                       (__attribute__((address_space(3))) void*)(d + ch * 256), 4, 0, 0);
+  }
+}
+
+template <typename TP>
+__global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, GridSync gs) {
+  extern __shared__ double lds[];
+  // per-draw metadata: blocks, their sizes, panel offsets and step coefficients
+  __shared__ int s_j[kRing], s_i[kRing], s_nJ[kRing], s_nI[kRing];
+  __shared__ int64_t s_c0[kRing], s_r0[kRing];
+  __shared__ double s_cc[kRing], s_cr[kRing];
+  __shared__ int s_ok;
+  __shared__ double s_err2;
+  const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
+  const int64_t m = a.m, n = a.n;
+  const int MJ = a.max_nJ, MI = a.max_nI;
+  const GridLayout L = grid_layout(m, n, MI, MJ, G, T);
+  const int64_t r0 = (int64_t)w * m / G, r1 = (int64_t)(w + 1) * m / G;
+  const int64_t cA = (int64_t)w * n / G, cB = (int64_t)(w + 1) * n / G;
+  const int nr = (int)(r1 - r0), nc = (int)(cB - cA);
+
+  double* z = lds;          // z on owned rows
+  double* zp = z + L.NR;    // previous z (returned when the stop rule fires one iteration late)
+  double* bl = zp + L.NR;   // b on owned rows
+  double* x = bl + L.NR;    // x on owned columns
+  double* xr = x + L.NC;    // x_ref on owned columns
+  double* v = xr + L.NC;    // reduced A_{:,J}^T z
+  double* u = v + MJ;       // reduced A_{I,:} x - b_I + z_I
+  double* red2 = u + MI;    // T scratch
+  TP* slabC = (TP*)(lds + L.dbl);
+  TP* slabR = slabC + 2 * L.slabC;
+
+  const TP* __restrict__ Arow = (const TP*)a.Arow;
+  const TP* __restrict__ Acol = (const TP*)a.Acol;
+  const int NG = gs.groups, g = w % NG;
+  const int gsize = (G - g + NG - 1) / NG;
+  const int E = gs.stride;
+  const int err_slot = MJ + MI;
+  const bool leader = w < NG;  // workgroup g collects group g
+  const int64_t K = a.max_iter;
+  const int64_t ce = a.check_every > 0 ? a.check_every : 1;
+  const bool checking = a.x_ref != nullptr && a.tol > 0.0;
+  const int tpr = lanes_per_item(T, nr);  // lanes per owned row in the z-update
+  const int tpc = lanes_per_item(T, nc);  // lanes per owned column in the x-update
+
+  for (int q = tid; q < nr; q += T) {
+    z[q] = a.z_in ? a.z_in[r0 + q] : a.b[r0 + q];
+    zp[q] = z[q];
+    bl[q] = a.b[r0 + q];
+  }
+  for (int q = tid; q < nc; q += T) {
+    x[q] = a.x_in ? a.x_in[cA + q] : 0.0;
+    xr[q] = a.x_ref ? a.x_ref[cA + q] : 0.0;
+  }
+
+  auto refill = [&](int64_t first) {  // draws of relative iterations first .. first+63
+    if (tid < 64) {
+      const int64_t q = first + tid;
+      if (q <= K) {
+        int jj, ii;
+        draw_pair(a, a.k0 + q, jj, ii);
+        const int sl = (int)((q - 1) & (kRing - 1));
+        s_j[sl] = jj;
+        s_i[sl] = ii;
+        s_c0[sl] = a.col_off[jj];
+        s_nJ[sl] = (int)(a.col_off[jj + 1] - a.col_off[jj]);
+        s_r0[sl] = a.row_off[ii];
+        s_nI[sl] = (int)(a.row_off[ii + 1] - a.row_off[ii]);
+        s_cc[sl] = a.coef_col[jj];
+        s_cr[sl] = a.coef_row[ii];
+      }
+    }
+  };
+  auto slot = [&](int64_t q) -> int { return (int)((q - 1) & (kRing - 1)); };
+  refill(1);
+  refill(65);
+  __syncthreads();
+  int64_t filled_to = 128;
+
+  // Slab sources as one concatenated range: [0, lc) from the column panel of the draw of
+  // iteration qc (owned rows), [lc, lc + lr) from the row panel of the draw of iteration qr
+  // (owned columns).  qc / qr < 1: none.
+  struct Src {
+    const TP* c;
+    int lc;
+    const TP* r;
+    int lr;
+  };
+  auto slab_src = [&](int64_t qc, int64_t qr) -> Src {
+    Src sr{nullptr, 0, nullptr, 0};
+    if (qc >= 1) {
+      const int sl = slot(qc);
+      sr.c = Acol + m * s_c0[sl] + r0 * s_nJ[sl];
+      sr.lc = nr * s_nJ[sl];
+    }
+    if (qr >= 1) {
+      const int sl = slot(qr);
+      sr.r = Arow + n * s_r0[sl] + cA * s_nI[sl];
+      sr.lr = nc * s_nI[sl];
+    }
+    return sr;
+  };
+
+  // One grid-wide reduction of this round's partial vectors (entries [0, nq), [MJ, MJ + np) and,
+  // with has_err, err_slot; every workgroup has published them tagged with `epoch`).  The leader
+  // of each group polls its members' tagged entries, sums them in member order and publishes the
+  // tagged group sum; every workgroup then waits for the group sums and adds them in group order.
+  // While the sums travel, waves 1..3 load the next round's slabs (column slab of iteration qc
+  // into column buffer bufC, row slab of iteration qr into row buffer bufR).  On return v, u and
+  // s_err2 hold the reduced values.  Returns false after a spin-limit timeout.
+  auto need = [&](int e, int nq, int np, bool has_err) -> bool {
+    return e < nq || (e >= MJ && e < MJ + np) || (has_err && e == err_slot);
+  };
+  auto sync_round = [&](unsigned epoch, int par, int nq, int np, bool has_err, int64_t qc, int bufC, int64_t qr,
+                        int bufR) -> bool {
+    int ok = 1;
+    if (tid == 0) s_ok = 1;  // (the previous reader of s_ok passed a barrier since)
+    unsigned spins = 0;
+    auto give_up = [&]() -> bool {  // bounded waiting; true when this thread must stop waiting
+      if ((++spins & 63u) == 0) {
+        if (__hip_atomic_load(gs.timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+        if (spins > kSpinLimit) {
+          __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return true;
+        }
+      }
+      return false;
+    };
+    const bool any = nq > 0 || np > 0 || has_err;
+    if (leader && any) {
+      const unsigned long long* P = gs.part + (size_t)par * G * E * 2;
+      unsigned long long* Gs = gs.gsum + ((size_t)(epoch % kSumRing) * NG + g) * E * 2;
+      for (int e = tid; e < E && ok; e += T) {
+        if (!need(e, nq, np, has_err)) continue;
+        double s = 0.0;  // member order g, g + NG, ...
+        for (int q0 = 0; q0 < gsize && ok; q0 += 16) {
+          const int cnt = gsize - q0 < 16 ? gsize - q0 : 16;
+          unsigned pending = (1u << cnt) - 1u;
+          double vals[16];
+          while (pending) {
+            unsigned long long w0[16], w1[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+              const int qq = q0 + q < gsize ? q0 + q : gsize - 1;
+              const unsigned long long* src = P + ((size_t)(g + qq * NG) * E + e) * 2;
+              w0[q] = ld_u64(src);
+              w1[q] = ld_u64(src + 1);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+              if (((pending >> q) & 1u) && tag_ok(w0[q], w1[q], epoch)) {
+                vals[q] = tag_value(w0[q], w1[q]);
+                pending &= ~(1u << q);
+              }
+            if (pending && give_up()) { ok = 0; break; }
+          }
+#pragma unroll
+          for (int q = 0; q < 16; ++q) s += (q < cnt) ? vals[q] : 0.0;
+        }
+        st_tagged(Gs + (size_t)e * 2, s, epoch);
+      }
+    }
+    const Src sr = slab_src(qc, qr);
+    TP* dC = slabC + (size_t)bufC * L.slabC;
+    TP* dR = slabR + (size_t)bufR * L.slabR;
+    const int dmaC = dma_bytes(sr.c, sr.lc), dmaR = dma_bytes(sr.r, sr.lr);
+    if (tid >= 64) {  // waves 1..3: start the copies of the next slabs straight into LDS
+      dma_to_lds(sr.c, dC, dmaC);
+      dma_to_lds(sr.r, dR, dmaR);
+    }
+    const unsigned long long* Gall = gs.gsum + (size_t)(epoch % kSumRing) * NG * E * 2;
+    // wave 0 watches one entry of every group (the highest one reduced this round)
+    if (tid < 64 && any) {
+      const int ed = has_err ? err_slot : (np > 0 ? MJ + np - 1 : nq - 1);
+      bool seen = tid >= NG;
+      while (ok) {
+        if (!seen) {
+          const unsigned long long* src = Gall + ((size_t)tid * E + ed) * 2;
+          const unsigned long long w0 = ld_u64(src), w1 = ld_u64(src + 1);
+          seen = tag_ok(w0, w1, epoch);
+        }
+        if (__all(seen)) break;
+        if (give_up()) ok = 0;
+      }
+      if (!ok) s_ok = 0;
+    }
+    __syncthreads();
+    if (s_ok == 0) ok = 0;
+    // every needed entry: the NG tagged group sums, added in group order.  The first read goes
+    // through the XCD's L2 (workgroup-scope loads), so the 32 workgroups of an XCD fetch the
+    // group sums from memory once; a pair whose tag is not current (a stale cached line, or a
+    // late store) is re-read at device scope until it is.
+    for (int e = tid; e < E && ok; e += T) {
+      if (!need(e, nq, np, has_err)) continue;
+      double vals[16];
+      unsigned pending = (1u << NG) - 1u;
+      bool cached = true;
+      while (pending) {
+        unsigned long long w0[16], w1[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const unsigned long long* src = Gall + ((size_t)(q < NG ? q : NG - 1) * E + e) * 2;
+          w0[q] = cached ? ld_u64_cached(src) : ld_u64(src);
+          w1[q] = cached ? ld_u64_cached(src + 1) : ld_u64(src + 1);
+        }
+        cached = false;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (((pending >> q) & 1u) && tag_ok(w0[q], w1[q], epoch)) {
+            vals[q] = tag_value(w0[q], w1[q]);
+            pending &= ~(1u << q);
+          }
+        if (pending && give_up()) { ok = 0; break; }
+      }
+      if (!ok) break;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) s += (q < NG) ? vals[q] : 0.0;
+      if (e < MJ) v[e] = s;
+      else if (e < MJ + MI) u[e - MJ] = s;
+      else s_err2 = s;
+    }
+    // elements the copy engine could not take (unaligned or odd-sized tails), then wait for the
+    // copies this wave started
+    for (int idx = dmaC / (int)sizeof(TP) + tid; idx < sr.lc; idx += T) dC[idx] = sr.c[idx];
+    for (int idx = dmaR / (int)sizeof(TP) + tid; idx < sr.lr; idx += T) dR[idx] = sr.r[idx];
+    wait_mem();
+    if (!ok) s_ok = 0;
+    __syncthreads();
+    const bool all_ok = s_ok != 0;
+    return all_ok;
+  };
+
+  // z <- z - coef * A_{R,J} v on owned rows (row-major slab nr x nJ); keeps the previous z.
+  auto zupdate = [&](const TP* Sl, int nJ, double coef) {
+    const int rp = T / tpr, sub = tid % tpr;
+    for (int q0 = 0; q0 < nr; q0 += rp) {
+      const int q = q0 + tid / tpr;
+      double acc = 0.0;
+      if (q < nr) {
+        const TP* row = Sl + (size_t)q * nJ;
+#pragma unroll 4
+        for (int c = sub; c < nJ; c += tpr) acc += widen(row[c]) * v[c];
+      }
+      acc = group_sum(acc, tpr);
+      if (q < nr && sub == 0) {
+        zp[q] = z[q];
+        z[q] -= coef * acc;
+      }
+    }
+  };
+  // x <- x - coef * A_{I,C}^T u on owned columns (column-major slab nc x nI)
+  auto xupdate = [&](const TP* Sl, int nI, double coef) {
+    const int cp = T / tpc, sub = tid % tpc;
+    for (int c0 = 0; c0 < nc; c0 += cp) {
+      const int cc = c0 + tid / tpc;
+      double acc = 0.0;
+      if (cc < nc) {
+        const TP* col = Sl + (size_t)cc * nI;
+#pragma unroll 4
+        for (int l = sub; l < nI; l += tpc) acc += widen(col[l]) * u[l];
+      }
+      acc = group_sum(acc, tpc);
+      if (cc < nc && sub == 0) x[cc] -= coef * acc;
+    }
+  };
+  // column sums of a row-major slab (nr x nJ) weighted by z: row-group partials into red2
+  auto colsum_partial = [&](const TP* Sl, int nJ) {
+    const int ng = T / nJ, gq = tid / nJ, c = tid % nJ;
+    double acc = 0.0;
+    if (gq < ng) {
+#pragma unroll 4
+      for (int q = gq; q < nr; q += ng) acc += widen(Sl[q * nJ + c]) * z[q];
+    }
+    red2[tid] = acc;
+  };
+  auto colsum_finish = [&](int nJ, unsigned long long* P, unsigned ep) {
+    if (tid < nJ) {
+      const int ng = T / nJ;
+      double s = 0.0;
+      for (int q = 0; q < ng; ++q) s += red2[q * nJ + tid];
+      st_tagged(P + (size_t)tid * 2, s, ep);
+    }
+  };
+  // partial error ||x - x_ref||^2 over owned columns (wave 0)
+  auto err_partial = [&](unsigned long long* P, unsigned ep) {
+    if (tid < 64) {
+      double e = 0.0;
+      for (int cc = tid; cc < nc; cc += 64) {
+        const double d = x[cc] - xr[cc];
+        e += d * d;
+      }
+      e = wave_sum(e);
+      if (tid == 0) st_tagged(P + (size_t)err_slot * 2, e, ep);
+    }
+  };
+
+  unsigned epoch = 0;
+  int status = 0, stopped = 0;
+  int64_t last_k = a.k0;
+  double last_err2 = -1.0;
+  int64_t last_check = -1;
+  bool alive = true;
+
+  // ---------------- prologue: partial sums of v^1 = A_{:,J_1}^T z^0
+  {
+    const Src s1 = slab_src(1, 0);
+    TP* d1 = slabC + 1 * L.slabC;  // the column slab of iteration q lives in buffer q & 1
+    for (int idx = tid; idx < s1.lc; idx += T) d1[idx] = s1.c[idx];
+    __syncthreads();
+    const int nJ1 = s_nJ[slot(1)];
+    colsum_partial(d1, nJ1);
+    __syncthreads();
+    colsum_finish(nJ1, gs.part + (size_t)w * E * 2, epoch + 1);
+    alive = sync_round(++epoch, 0, nJ1, 0, false, K >= 2 ? 2 : 0, 0, 1, 1);
+  }
+
+  int64_t rr = 1;
+  for (; alive && rr <= K; ++rr) {
+    const int64_t k = a.k0 + rr;
+    if (rr + 34 > filled_to && filled_to < K) {
+      refill(filled_to + 1);
+      filled_to += 64;
+      __syncthreads();
+    }
+    const int sk = slot(rr);
+    const int nJk = s_nJ[sk], nIk = s_nI[sk];
+    const int nIp = rr >= 2 ? s_nI[slot(rr - 1)] : 0;
+    const int nJn = rr < K ? s_nJ[slot(rr + 1)] : 0;
+    if (w == 0 && tid == 0 && a.trace_j) {
+      a.trace_j[rr - 1] = s_j[sk];
+      a.trace_i[rr - 1] = s_i[sk];
+    }
+
+    // phase A: z^k on owned rows (column slab of J_k); x^{k-1} on owned columns (row slab of I_{k-1})
+    zupdate(slabC + (size_t)(rr & 1) * L.slabC, nJk, s_cc[sk]);
+    if (nIp > 0 && nc > 0) xupdate(slabR + (size_t)((rr - 1) & 1) * L.slabR, nIp, s_cr[slot(rr - 1)]);
+    __syncthreads();
+    // phase B: this workgroup's partial vector: A_{:,J_{k+1}}^T z^k (row groups), A_{I_k,C} x^{k-1}
+    // + (z^k - b) on owned rows of I_k, and ||x^{k-1} - x_ref||^2
+    unsigned long long* P = gs.part + ((size_t)(rr & 1) * G + w) * E * 2;
+    const unsigned ep = epoch + 1;
+    const bool has_err = checking && rr >= 2 && ((rr - 1) % ce == 0);
+    if (nJn > 0) colsum_partial(slabC + (size_t)((rr + 1) & 1) * L.slabC, nJn);
+    {
+      const TP* Sr = slabR + (size_t)(rr & 1) * L.slabR;
+      const int64_t rI = s_r0[sk];
+      for (int l = tid; l < nIk; l += T) {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int cc = 0; cc < nc; ++cc) acc += widen(Sr[cc * nIk + l]) * x[cc];
+        const int64_t gl = rI + l;
+        if (gl >= r0 && gl < r1) acc += z[gl - r0] - bl[gl - r0];
+        st_tagged(P + (size_t)(MJ + l) * 2, acc, ep);
+      }
+    }
+    if (has_err) err_partial(P, ep);
+    __syncthreads();
+    if (nJn > 0) colsum_finish(nJn, P, ep);
+    alive = sync_round(++epoch, (int)(rr & 1), nJn, nIk, has_err, rr + 2 <= K ? rr + 2 : 0, (int)(rr & 1),
+                       rr + 1 <= K ? rr + 1 : 0, (int)((rr + 1) & 1));
+    if (!alive) break;
+    // v = v^{k+1}, u = u^k, s_err2 = ||x^{k-1} - x_ref||^2
+    if (has_err) {
+      const double e2 = s_err2;
+      last_err2 = e2;
+      last_check = k - 1;
+      const double rel = sqrt(e2) / sqrt(a.xref_sq);
+      if (rel < a.tol || !isfinite(e2) || rel > 1e6) {
+        stopped = 1;
+        status = rel < a.tol ? 0 : 2;
+        last_k = k - 1;
+        for (int q = tid; q < nr; q += T) z[q] = zp[q];  // z^{k-1}
+        __syncthreads();
+        break;
+      }
+    }
+  }
+
+  if (alive && !stopped) {
+    // epilogue: x^K from u^K, then the error of x^K
+    const int sK = slot(K);
+    if (nc > 0) xupdate(slabR + (size_t)(K & 1) * L.slabR, s_nI[sK], s_cr[sK]);
+    __syncthreads();
+    last_k = a.k0 + K;
+    if (a.x_ref != nullptr) {
+      const int par = (int)((K + 1) & 1);
+      err_partial(gs.part + ((size_t)par * G + w) * E * 2, epoch + 1);
+      alive = sync_round(++epoch, par, 0, 0, true, 0, 0, 0, 0);
+      if (alive) {
+        last_err2 = s_err2;
+        last_check = a.k0 + K;
+        if (checking) {
+          const double rel = sqrt(last_err2) / sqrt(a.xref_sq);
+          if (rel < a.tol) {
+            stopped = 1;
+            status = 0;
+          } else if (!isfinite(last_err2) || rel > 1e6) {
+            stopped = 1;
+            status = 2;
+          } else {
+            status = 1;
+          }
+        }
+      }
+    }
+  }
+
+  for (int q = tid; q < nr; q += T)
+    if (a.z_out) a.z_out[r0 + q] = z[q];
+  for (int q = tid; q < nc; q += T) a.x_out[cA + q] = x[q];
+  if (w == 0 && tid == 0) {
+    a.status->status = alive ? status : -4;
+    a.status->stopped = stopped;
+    a.status->last_k = last_k;
+    a.status->err2 = last_err2;
+    a.status->check_k = last_check;
+  }
+}
+
+}  // namespace
+
+size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype) {
+  const GridLayout L = grid_layout(a.m, a.n, a.max_nI, a.max_nJ, grid, kGridThreads);
+  const size_t esz = panel_dtype == 0 ? 8 : (panel_dtype == 1 ? 4 : 2);
+  return L.dbl * sizeof(double) + 2 * (L.slabC + L.slabR) * esz + 64;
+}
+
+hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    hipError_t e = hipFuncSetAttribute((const void*)grid_solve_kernel<TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)grid_solve_kernel<TP>, kGridThreads,
+                                                        lds_bytes);
+  });
+}
+
+hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_dtype, int grid, hipStream_t st) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    const size_t lds = grid_solve_lds_bytes(a, grid, panel_dtype);
+    hipError_t e = hipFuncSetAttribute((const void*)grid_solve_kernel<TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    SolveArgs aa = a;
+    GridSync gg = gs;
+    void* args[] = {&aa, &gg};
+    return hipLaunchCooperativeKernel((const void*)grid_solve_kernel<TP>, dim3(grid), dim3(kGridThreads), args,
+                                      (unsigned)lds, st);
+  });
+}
+
+}  // namespace rebk

@@ -45,14 +45,13 @@ struct SolveArgs {
   DevStatus* status;
 };
 
-// Synchronisation workspace of the persistent grid kernel.
+// Synchronisation workspace of the persistent grid kernel (zeroed before every launch).
 struct GridSync {
-  unsigned* bar;      // counters and release flags, zeroed before every launch
-  double* acc;        // 3 x stripes x stride accumulators, zeroed before every launch
-  int* timeout;       // set when a barrier exceeded its spin limit
-  int32_t stripes;
-  int32_t stride;     // entries per stripe (>= max_nJ + max_nI + 1)
-  int32_t groups;     // first-level barrier groups
+  unsigned long long* part;  // 2 x grid x stride epoch-tagged pairs: per-workgroup partial vectors
+  unsigned long long* gsum;  // 32 x groups x stride epoch-tagged pairs: per-group sums (ring)
+  int* timeout;              // set when a wait exceeded its spin limit
+  int32_t stride;            // entries per partial vector (>= max_nJ + max_nI + 1)
+  int32_t groups;            // reduction groups (<= 16)
 };
 
 // Launchers (defined in rebk_kernels.hip).  All return hipError_t.
