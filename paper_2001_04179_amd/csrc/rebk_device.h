@@ -89,31 +89,33 @@ __device__ __forceinline__ double wg_sum(double val, double* red) {
   return s;
 }
 
-// out[c] = sum_{r < rows} P[r * w + c] * y[r] for c < w, P row-major (rows x w) in any memory,
-// y in LDS.  Threads form T / w row groups per column; partial sums meet in red (blockDim slots).
-// Columns beyond blockDim.x are processed in chunks.  Ends with a barrier.
+// out[c] = sum_{r < rows} P[c * rows + r] * y[r] for c < w, P column-major (rows x w) in any
+// memory, y in LDS.  Each column gets T / w consecutive threads (coalesced along r); partial sums
+// meet in red (blockDim slots).  Columns beyond blockDim.x are processed in chunks.  Ends with a
+// barrier.
 template <typename TP>
-__device__ __forceinline__ void colsum_rowmajor(const TP* __restrict__ P, int64_t rows, int w, const double* y,
+__device__ __forceinline__ void colsum_colmajor(const TP* __restrict__ P, int64_t rows, int w, const double* y,
                                                 double* out, double* red) {
   const int T = blockDim.x, tid = threadIdx.x;
   for (int cb = 0; cb < w; cb += T) {
     const int cw = min(T, w - cb);
-    const int ng = T / cw;
-    const int g = tid / cw, c = cb + tid % cw;
+    const int gpc = T / cw;  // threads per column
+    const int c = cb + tid / gpc, g = tid % gpc;
     double acc = 0.0;
-    if (g < ng)
-      for (int64_t r = g; r < rows; r += ng) acc += widen(P[r * w + c]) * y[r];
+    if (tid / gpc < cw) {
+      const TP* col = P + (int64_t)c * rows;
+      for (int64_t r = g; r < rows; r += gpc) acc += widen(col[r]) * y[r];
+    }
     red[tid] = acc;
     __syncthreads();
     if (tid < cw) {
       double s = 0.0;
-      for (int q = 0; q < ng; ++q) s += red[q * cw + tid];
+      for (int q = 0; q < gpc; ++q) s += red[tid * gpc + q];
       out[cb + tid] = s;
     }
     __syncthreads();
   }
 }
-
 
 template <typename F>
 hipError_t dispatch_panel(int dt, F&& f) {

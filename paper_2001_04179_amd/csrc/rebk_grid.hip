@@ -9,23 +9,22 @@
 // The z-chain never reads x, so running the x-chain one iteration behind the z-chain is exact and
 // needs a single synchronisation per iteration.
 //
-// The reduction is a deterministic two-level tree merged into the grid barrier: each workgroup
-// stores its partial vector; the last arrival of each group of workgroups (group g holds
-// workgroups g, g+NG, g+2NG, ...) sums its group in member order and stores the group sum; the
-// last group to arrive releases everyone; every workgroup then sums the NG group sums in group
-// order.  All workgroups therefore see bit-identical reduced vectors, and a run is reproducible
-// bit for bit.
+// Reduction: a deterministic two-level tree without counters or fences.  Every value crossing
+// workgroups is published as two 64-bit atomic words that both carry the iteration's epoch, so a
+// reader can tell a current value from a stale or half-written one.  Workgroup w belongs to group
+// g = w mod NG, whose leader is workgroup g: the leader polls its members' tagged partial vectors,
+// sums them in member order and publishes the tagged group sum; every workgroup waits for the NG
+// group sums and adds them in group order.  All workgroups therefore see bit-identical reduced
+// vectors and a run is reproducible bit for bit.  All cross-workgroup traffic uses device-scope
+// atomic loads and stores, coherent across the eight XCDs without cache maintenance (an
+// agent-scope release fence writes back the XCD's L2 and costs microseconds on gfx950).
 //
-// All cross-workgroup traffic uses device-scope atomic loads and stores (coherent across the
-// eight XCDs without cache-maintenance fences); a workgroup waits for its stores to complete
-// (s_waitcnt vmcnt(0)) before it arrives.  An agent-scope release fence would write back the
-// XCD's L2 and costs microseconds per workgroup on gfx950.
-//
-// Panel slabs: the column slab A_{R_w, J} (owned rows, row-major, contiguous in the column panel)
-// and the row slab A_{I, C_w} (owned columns, column-major, contiguous in the row panel) are read
-// from HBM once each: for the partial sums of one round and, from LDS, for the update of the
-// next.  Because the block sequence depends only on the counter-based generator, the slabs of
-// the next round are loaded into registers while the barrier spins and land in LDS right after.
+// Panel slabs: the column slab A_{R_w, J} (owned rows; column panels hold A^T, so the slab is |J|
+// runs of the owned rows) and the row slab A_{I, C_w} (owned columns, contiguous in the
+// column-major row panel) are read from HBM once each: for the partial sums of one round and,
+// from LDS, for the update of the next.  Because the block sequence depends only on the
+// counter-based generator, waves 1..3 copy the next round's slabs straight into LDS with
+// global_load_lds while the reduction is in flight.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -103,36 +102,46 @@ __device__ __forceinline__ int lanes_per_item(int threads, int items) {
   return p;
 }
 
-// Sum over aligned groups of `width` lanes (width a power of two <= 64); every lane gets the sum.
+// Data-parallel-primitive lane exchange of an FP64 value (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+// Sum over aligned groups of `width` lanes (a power of two <= 64); every lane of a group gets the
+// group's sum.  Quad permutations, half-row and row mirrors stay inside a row of 16 lanes.
 __device__ __forceinline__ double group_sum(double v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (width >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  if (width >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (width >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+  if (width >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+  if (width >= 32) v += __shfl_xor(v, 16, 64);
+  if (width >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
 constexpr int kRing = 128;  // block draws kept ahead (relative iteration q in slot (q - 1) & 127)
 
-// Bytes of a panel range that go through the LDS copy path: the 4-byte-aligned whole-dword
-// prefix (0 if the start is not 4-byte aligned).
+// Copy `runs` runs of `len` panel elements (run r starts at src + r * stride, lands at
+// dst + r * len) into LDS.  Waves 1..3 issue global_load_lds copies (one dword per lane, up to 256
+// bytes per wave instruction; asynchronous, complete for the issuing wave after
+// s_waitcnt vmcnt(0)).  Returns false when the runs are not whole 4-byte-aligned dwords (2-byte
+// panels), in which case nothing was issued.
 template <typename TP>
-__device__ __forceinline__ int dma_bytes(const TP* src, int elems) {
-  if (src == nullptr || (reinterpret_cast<uintptr_t>(src) & 3u) != 0) return 0;
-  return (int)((elems * sizeof(TP)) & ~(size_t)3);
-}
-
-// Waves 1..3 copy nbytes (a multiple of 4) from global memory into LDS with global_load_lds
-// (asynchronous, no registers): one dword per lane, 256 bytes per wave instruction.  The copy is
-// complete for the issuing wave after s_waitcnt vmcnt(0).
-__device__ __forceinline__ void dma_to_lds(const void* src, void* dst, int nbytes) {
+__device__ __forceinline__ bool dma_runs(const TP* src, int64_t stride, int runs, int len, TP* dst) {
+  if (sizeof(TP) < 4) return false;
   const int wave = (int)(threadIdx.x >> 6) - 1, lane = (int)(threadIdx.x & 63);
-  const int nchunks = (nbytes + 255) >> 8;
-  const char* s = (const char*)src;
-  char* d = (char*)dst;
-  for (int ch = wave; ch < nchunks; ch += 3) {
-    const int off = ch * 256 + lane * 4;
-    if (off < nbytes)
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off),
-                                       (__attribute__((address_space(3))) void*)(d + ch * 256), 4, 0, 0);
+  const int bytes = len * (int)sizeof(TP);
+  for (int r = wave; r < runs; r += 3) {
+    const char* s = (const char*)(src + (int64_t)r * stride);
+    char* d = (char*)(dst + (size_t)r * len);
+    for (int off = 0; off < bytes; off += 256)
+      if (off + lane * 4 < bytes)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off + lane * 4),
+                                         (__attribute__((address_space(3))) void*)(d + off), 4, 0, 0);
   }
+  return true;
 }
 
 template <typename TP>
@@ -159,7 +168,6 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   double* xr = x + L.NC;    // x_ref on owned columns
   double* v = xr + L.NC;    // reduced A_{:,J}^T z
   double* u = v + MJ;       // reduced A_{I,:} x - b_I + z_I
-  double* red2 = u + MI;    // T scratch
   TP* slabC = (TP*)(lds + L.dbl);
   TP* slabR = slabC + 2 * L.slabC;
 
@@ -173,7 +181,6 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   const int64_t K = a.max_iter;
   const int64_t ce = a.check_every > 0 ? a.check_every : 1;
   const bool checking = a.x_ref != nullptr && a.tol > 0.0;
-  const int tpr = lanes_per_item(T, nr);  // lanes per owned row in the z-update
   const int tpc = lanes_per_item(T, nc);  // lanes per owned column in the x-update
 
   for (int q = tid; q < nr; q += T) {
@@ -210,28 +217,35 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   __syncthreads();
   int64_t filled_to = 128;
 
-  // Slab sources as one concatenated range: [0, lc) from the column panel of the draw of
-  // iteration qc (owned rows), [lc, lc + lr) from the row panel of the draw of iteration qr
-  // (owned columns).  qc / qr < 1: none.
+  // Column slab: nJ runs of nr elements (column panels hold A^T), stored run after run in LDS, so
+  // entry (q, c) of the slab sits at c * nr + q.  Row slab: one run of nc * nI elements, entry
+  // (l, c) at c * nI + l.
   struct Src {
     const TP* c;
-    int lc;
+    int runs;
     const TP* r;
     int lr;
   };
   auto slab_src = [&](int64_t qc, int64_t qr) -> Src {
     Src sr{nullptr, 0, nullptr, 0};
-    if (qc >= 1) {
+    if (qc >= 1 && nr > 0) {
       const int sl = slot(qc);
-      sr.c = Acol + m * s_c0[sl] + r0 * s_nJ[sl];
-      sr.lc = nr * s_nJ[sl];
+      sr.c = Acol + m * s_c0[sl] + r0;
+      sr.runs = s_nJ[sl];
     }
-    if (qr >= 1) {
+    if (qr >= 1 && nc > 0) {
       const int sl = slot(qr);
       sr.r = Arow + n * s_r0[sl] + cA * s_nI[sl];
       sr.lr = nc * s_nI[sl];
     }
     return sr;
+  };
+  auto copy_plain = [&](const Src& sr, TP* dC, TP* dR) {  // every thread, ordinary loads
+    for (int e = tid; e < sr.runs * nr; e += T) {
+      const int c = e / nr, q = e - c * nr;
+      dC[e] = sr.c[(int64_t)c * m + q];
+    }
+    for (int e = tid; e < sr.lr; e += T) dR[e] = sr.r[e];
   };
 
   // One grid-wide reduction of this round's partial vectors (entries [0, nq), [MJ, MJ + np) and,
@@ -296,10 +310,10 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     const Src sr = slab_src(qc, qr);
     TP* dC = slabC + (size_t)bufC * L.slabC;
     TP* dR = slabR + (size_t)bufR * L.slabR;
-    const int dmaC = dma_bytes(sr.c, sr.lc), dmaR = dma_bytes(sr.r, sr.lr);
+    bool dma = false;
     if (tid >= 64) {  // waves 1..3: start the copies of the next slabs straight into LDS
-      dma_to_lds(sr.c, dC, dmaC);
-      dma_to_lds(sr.r, dR, dmaR);
+      dma = dma_runs(sr.c, m, sr.runs, nr, dC);
+      dma_runs(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
     }
     const unsigned long long* Gall = gs.gsum + (size_t)(epoch % kSumRing) * NG * E * 2;
     // wave 0 watches one entry of every group (the highest one reduced this round)
@@ -353,10 +367,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       else if (e < MJ + MI) u[e - MJ] = s;
       else s_err2 = s;
     }
-    // elements the copy engine could not take (unaligned or odd-sized tails), then wait for the
-    // copies this wave started
-    for (int idx = dmaC / (int)sizeof(TP) + tid; idx < sr.lc; idx += T) dC[idx] = sr.c[idx];
-    for (int idx = dmaR / (int)sizeof(TP) + tid; idx < sr.lr; idx += T) dR[idx] = sr.r[idx];
+    // 2-byte panels are copied with ordinary loads; then wait for the copies this wave started
+    if (sizeof(TP) < 4) copy_plain(sr, dC, dR);
+    (void)dma;
     wait_mem();
     if (!ok) s_ok = 0;
     __syncthreads();
@@ -364,22 +377,21 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     return all_ok;
   };
 
-  // z <- z - coef * A_{R,J} v on owned rows (row-major slab nr x nJ); keeps the previous z.
+  // z <- z - coef * A_{R,J} v on owned rows (slab entry (q, c) at c * nr + q); keeps the previous z.
   auto zupdate = [&](const TP* Sl, int nJ, double coef) {
-    const int rp = T / tpr, sub = tid % tpr;
-    for (int q0 = 0; q0 < nr; q0 += rp) {
-      const int q = q0 + tid / tpr;
-      double acc = 0.0;
-      if (q < nr) {
-        const TP* row = Sl + (size_t)q * nJ;
-#pragma unroll 4
-        for (int c = sub; c < nJ; c += tpr) acc += widen(row[c]) * v[c];
+    for (int q = tid; q < nr; q += T) {
+      const TP* row = Sl + q;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int c = 0;
+      for (; c + 3 < nJ; c += 4) {
+        a0 += widen(row[(c + 0) * nr]) * v[c + 0];
+        a1 += widen(row[(c + 1) * nr]) * v[c + 1];
+        a2 += widen(row[(c + 2) * nr]) * v[c + 2];
+        a3 += widen(row[(c + 3) * nr]) * v[c + 3];
       }
-      acc = group_sum(acc, tpr);
-      if (q < nr && sub == 0) {
-        zp[q] = z[q];
-        z[q] -= coef * acc;
-      }
+      for (; c < nJ; ++c) a0 += widen(row[c * nr]) * v[c];
+      zp[q] = z[q];
+      z[q] -= coef * ((a0 + a1) + (a2 + a3));
     }
   };
   // x <- x - coef * A_{I,C}^T u on owned columns (column-major slab nc x nI)
@@ -397,22 +409,24 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       if (cc < nc && sub == 0) x[cc] -= coef * acc;
     }
   };
-  // column sums of a row-major slab (nr x nJ) weighted by z: row-group partials into red2
-  auto colsum_partial = [&](const TP* Sl, int nJ) {
-    const int ng = T / nJ, gq = tid / nJ, c = tid % nJ;
-    double acc = 0.0;
-    if (gq < ng) {
-#pragma unroll 4
-      for (int q = gq; q < nr; q += ng) acc += widen(Sl[q * nJ + c]) * z[q];
-    }
-    red2[tid] = acc;
-  };
-  auto colsum_finish = [&](int nJ, unsigned long long* P, unsigned ep) {
-    if (tid < nJ) {
-      const int ng = T / nJ;
-      double s = 0.0;
-      for (int q = 0; q < ng; ++q) s += red2[q * nJ + tid];
-      st_tagged(P + (size_t)tid * 2, s, ep);
+  // publish A_{R,J}^T z over owned rows (slab entry (q, c) at c * nr + q) as entries [0, nJ):
+  // tq lanes per column, partial sums meet with lane exchanges
+  auto push_q = [&](const TP* Sl, int nJ, unsigned long long* P, unsigned ep) {
+    const int tq = lanes_per_item(T, nJ), per = T / tq, sub = tid % tq;
+    for (int c0 = 0; c0 < nJ; c0 += per) {
+      const int c = c0 + tid / tq;
+      double a0 = 0.0, a1 = 0.0;
+      if (c < nJ) {
+        const TP* col = Sl + (size_t)c * nr;
+        int q = sub;
+        for (; q + tq < nr; q += 2 * tq) {
+          a0 += widen(col[q]) * z[q];
+          a1 += widen(col[q + tq]) * z[q + tq];
+        }
+        if (q < nr) a0 += widen(col[q]) * z[q];
+      }
+      const double acc = group_sum(a0 + a1, tq);
+      if (c < nJ && sub == 0) st_tagged(P + (size_t)c * 2, acc, ep);
     }
   };
   // partial error ||x - x_ref||^2 over owned columns (wave 0)
@@ -437,14 +451,11 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 
   // ---------------- prologue: partial sums of v^1 = A_{:,J_1}^T z^0
   {
-    const Src s1 = slab_src(1, 0);
     TP* d1 = slabC + 1 * L.slabC;  // the column slab of iteration q lives in buffer q & 1
-    for (int idx = tid; idx < s1.lc; idx += T) d1[idx] = s1.c[idx];
+    copy_plain(slab_src(1, 0), d1, nullptr);
     __syncthreads();
     const int nJ1 = s_nJ[slot(1)];
-    colsum_partial(d1, nJ1);
-    __syncthreads();
-    colsum_finish(nJ1, gs.part + (size_t)w * E * 2, epoch + 1);
+    push_q(d1, nJ1, gs.part + (size_t)w * E * 2, epoch + 1);
     alive = sync_round(++epoch, 0, nJ1, 0, false, K >= 2 ? 2 : 0, 0, 1, 1);
   }
 
@@ -474,7 +485,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     unsigned long long* P = gs.part + ((size_t)(rr & 1) * G + w) * E * 2;
     const unsigned ep = epoch + 1;
     const bool has_err = checking && rr >= 2 && ((rr - 1) % ce == 0);
-    if (nJn > 0) colsum_partial(slabC + (size_t)((rr + 1) & 1) * L.slabC, nJn);
+    if (nJn > 0) push_q(slabC + (size_t)((rr + 1) & 1) * L.slabC, nJn, P, ep);
     {
       const TP* Sr = slabR + (size_t)(rr & 1) * L.slabR;
       const int64_t rI = s_r0[sk];
@@ -488,8 +499,6 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       }
     }
     if (has_err) err_partial(P, ep);
-    __syncthreads();
-    if (nJn > 0) colsum_finish(nJn, P, ep);
     alive = sync_round(++epoch, (int)(rr & 1), nJn, nIk, has_err, rr + 2 <= K ? rr + 2 : 0, (int)(rr & 1),
                        rr + 1 <= K ? rr + 1 : 0, (int)((rr + 1) & 1));
     if (!alive) break;

@@ -18,7 +18,7 @@ struct DevStatus {
 // Everything a solve kernel needs; device pointers unless noted.
 struct SolveArgs {
   const void* Arow;          // row panels: block i is an n x nI_i column-major panel at n*row_off[i]
-  const void* Acol;          // column panels: block j is an m x nJ_j row-major panel at m*col_off[j]
+  const void* Acol;          // column panels: A^T row-major; block j is an m x nJ_j column-major panel at m*col_off[j]
   const int64_t* row_off;    // s+1
   const int64_t* col_off;    // t+1
   const uint64_t* T_row;     // s cumulative 53-bit thresholds

@@ -43,16 +43,23 @@ __global__ void sample_kernel(const uint64_t* __restrict__ T_row, int s, const u
 
 // ------------------------------------------------------------------ packing
 
-// Column panels: block j is m x nJ_j, row-major, at offset m * col_off[j].
+// Column panels: A^T, row-major (n x m): entry (r, c) at c * m + r, so column block j is the
+// contiguous m x nJ_j column-major panel at offset m * col_off[j].  32 x 32 tiles through LDS.
 template <typename TIn, typename TP>
-__global__ void pack_col_kernel(const TIn* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                const int64_t* __restrict__ col_off, const int32_t* __restrict__ colblk,
-                                TP* __restrict__ Acol) {
-  for (int64_t r = blockIdx.y; r < m; r += gridDim.y) {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-      const int j = colblk[c];
-      const int64_t c0 = col_off[j], nJ = col_off[j + 1] - c0;
-      Acol[m * c0 + r * nJ + (c - c0)] = narrow<TP>((double)A[r * lda + c]);
+__global__ void pack_col_kernel(const TIn* __restrict__ A, int64_t lda, int64_t m, int64_t n, TP* __restrict__ Acol) {
+  __shared__ double tile[32][33];
+  for (int64_t R = (int64_t)blockIdx.y * 32; R < m; R += (int64_t)gridDim.y * 32) {
+    for (int64_t C = (int64_t)blockIdx.x * 32; C < n; C += (int64_t)gridDim.x * 32) {
+      for (int q = threadIdx.y; q < 32; q += blockDim.y) {
+        const int64_t r = R + q, c = C + threadIdx.x;
+        tile[q][threadIdx.x] = (r < m && c < n) ? (double)A[r * lda + c] : 0.0;
+      }
+      __syncthreads();
+      for (int q = threadIdx.y; q < 32; q += blockDim.y) {
+        const int64_t r = R + threadIdx.x, c = C + q;
+        if (r < m && c < n) Acol[c * m + r] = narrow<TP>(tile[threadIdx.x][q]);
+      }
+      __syncthreads();
     }
   }
 }
@@ -123,10 +130,10 @@ __global__ void colrow_sq_kernel(const TP* __restrict__ Acol, int64_t m, const i
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = e / m, r = e - j * m;
     const int64_t c0 = col_off[j], nJ = col_off[j + 1] - c0;
-    const TP* p = Acol + m * c0 + r * nJ;
+    const TP* p = Acol + m * c0 + r;
     double acc = 0.0;
     for (int64_t c = 0; c < nJ; ++c) {
-      const double v = widen(p[c]);
+      const double v = widen(p[c * m]);
       const double sq = v * v;
       acc = acc + sq;
     }
@@ -209,12 +216,12 @@ __global__ void __launch_bounds__(kWgThreads) wg_solve_kernel(SolveArgs a) {
     // z^k = z^{k-1} - alpha/||A_{:,J}||_F^2 * A_{:,J} (A_{:,J}^T z^{k-1})
     const int64_t c0 = a.col_off[j];
     const int nJ = (int)(a.col_off[j + 1] - c0);
-    const TP* __restrict__ P = Acol + m * c0;
-    colsum_rowmajor(P, m, nJ, z, v, red);
+    const TP* __restrict__ P = Acol + m * c0;  // (r, c) at c * m + r
+    colsum_colmajor(P, m, nJ, z, v, red);
     const double cc = a.coef_col[j];
     for (int64_t r = tid; r < m; r += T) {
       double acc = 0.0;
-      for (int c = 0; c < nJ; ++c) acc += widen(P[r * nJ + c]) * v[c];
+      for (int c = 0; c < nJ; ++c) acc += widen(P[c * m + r]) * v[c];
       z[r] -= cc * acc;
     }
     __syncthreads();
@@ -302,14 +309,11 @@ __global__ void residual_kernel(SolveArgs a, const double* __restrict__ x, const
     const double f = a.b[l] - z[l] - acc;
     f2 += f * f;
   }
-  // columns of A^T z through the column panels: entry (r, c) at m*c0 + r*nJ + (c - c0)
+  // columns of A^T z through the column panels (A^T, row-major): entry (r, c) at c * m + r
   for (int64_t c = (int64_t)blk * blockDim.x + tid; c < n; c += (int64_t)nb * blockDim.x) {
-    int lo = 0, hi = a.t - 1;
-    while (lo < hi) { const int mid = (lo + hi + 1) >> 1; if (a.col_off[mid] <= c) lo = mid; else hi = mid - 1; }
-    const int64_t c0 = a.col_off[lo], nJ = a.col_off[lo + 1] - c0;
-    const TP* p = Acol + m * c0 + (c - c0);
+    const TP* p = Acol + c * m;
     double acc = 0.0;
-    for (int64_t r = 0; r < m; ++r) acc += widen(p[r * nJ]) * z[r];
+    for (int64_t r = 0; r < m; ++r) acc += widen(p[r]) * z[r];
     g2 += acc * acc;
   }
   const double F = wg_sum(f2, red);
@@ -346,13 +350,13 @@ hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype,
     const unsigned ty = (unsigned)((m + 31) / 32 < 65535 ? (m + 31) / 32 : 65535);
     const unsigned tx = (unsigned)((n + 31) / 32 < 65535 ? (n + 31) / 32 : 65535);
     if (a_dtype == 0) {
-      hipLaunchKernelGGL((pack_col_kernel<double, TP>), dim3(gx, gy), dim3(256), 0, st, (const double*)A, lda, m, n,
-                         col_off_d, colblk_d, (TP*)Acol);
+      hipLaunchKernelGGL((pack_col_kernel<double, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const double*)A, lda, m, n,
+                         (TP*)Acol);
       hipLaunchKernelGGL((pack_row_kernel<double, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const double*)A, lda, m, n,
                          row_off_d, rowblk_d, (TP*)Arow);
     } else {
-      hipLaunchKernelGGL((pack_col_kernel<float, TP>), dim3(gx, gy), dim3(256), 0, st, (const float*)A, lda, m, n,
-                         col_off_d, colblk_d, (TP*)Acol);
+      hipLaunchKernelGGL((pack_col_kernel<float, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const float*)A, lda, m, n,
+                         (TP*)Acol);
       hipLaunchKernelGGL((pack_row_kernel<float, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const float*)A, lda, m, n,
                          row_off_d, rowblk_d, (TP*)Arow);
     }
