@@ -26,6 +26,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_FILE = "grid_solve_kernel_rank1500_20000x2000_traffic.json"
+# sources that define the solve kernel: measured traffic is reported only for the kernel it was taken on
+KERNEL_SOURCES = ("paper_2001_04179_amd/csrc/rebk_grid.hip", "paper_2001_04179_amd/csrc/rebk_device.h",
+                  "paper_2001_04179_amd/csrc/rebk_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -39,7 +52,23 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-iters", type=int, default=2000)
     p.add_argument("--scale", type=int, default=1, help="divide the problem dimensions (quick checks only)")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
+    p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", TRAFFIC_FILE),
+                   help="JSON with measured HBM bytes per launch of the solve kernel (from the counter runs)")
     return p.parse_args()
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 256 MiB, 5 times: the counter reference (bytes known)."""
+    import torch
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}))
 
 
 def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs):
@@ -85,6 +114,19 @@ def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs):
     }
 
 
+def traffic_for(path, panel):
+    """HBM bytes per launch of the solve kernel measured with the FETCH_SIZE / WRITE_SIZE counters
+    (scaled by a plain copy of known size), if a measurement file for this panel type is given."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None  # the kernel changed since the counters were taken
+    entry = data.get("panels", {}).get(panel)
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
 def cpu_baseline(S, iters_to_tol, sample_iters):
     import oracle
     t0 = time.perf_counter()
@@ -103,6 +145,9 @@ def cpu_baseline(S, iters_to_tol, sample_iters):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -130,7 +175,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": chosen["kernel_GBs"] / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": traffic_for(args.traffic_json, chosen_key),
         "kernel": "grid_solve_kernel",
         "bytes_per_iter": chosen["bytes_per_iter"],
     }

@@ -54,11 +54,13 @@ __device__ __forceinline__ void st_u64(unsigned long long* p, unsigned long long
 // A value published for one epoch: two 64-bit atomic words, each carrying the 32-bit epoch next
 // to one half of the FP64 bit pattern.  A reader accepts the pair only when both words carry the
 // epoch it waits for, so it never takes a stale value or a pair torn between two epochs; no fence
-// or counter is needed to order the data with its arrival.
-__device__ __forceinline__ void st_tagged(unsigned long long* p, double v, unsigned epoch) {
+// or counter is needed to order the data with its arrival.  A vector of E tagged values is stored
+// as two planes (first words at p[0, E), second words at p[E, 2E)), so the lanes of one store or
+// load instruction touch consecutive words.
+__device__ __forceinline__ void st_tagged(unsigned long long* p, int E, int e, double v, unsigned epoch) {
   const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-  st_u64(p, ((unsigned long long)epoch << 32) | (bits >> 32));
-  st_u64(p + 1, (bits << 32) | (unsigned long long)epoch);
+  st_u64(p + e, ((unsigned long long)epoch << 32) | (bits >> 32));
+  st_u64(p + E + e, (bits << 32) | (unsigned long long)epoch);
 }
 __device__ __forceinline__ bool tag_ok(unsigned long long w0, unsigned long long w1, unsigned epoch) {
   return (unsigned)(w0 >> 32) == epoch && (unsigned)w1 == epoch;
@@ -289,9 +291,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
               const int qq = q0 + q < gsize ? q0 + q : gsize - 1;
-              const unsigned long long* src = P + ((size_t)(g + qq * NG) * E + e) * 2;
+              const unsigned long long* src = P + (size_t)(g + qq * NG) * E * 2 + e;
               w0[q] = ld_u64(src);
-              w1[q] = ld_u64(src + 1);
+              w1[q] = ld_u64(src + E);
             }
 #pragma unroll
             for (int q = 0; q < 16; ++q)
@@ -304,7 +306,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 #pragma unroll
           for (int q = 0; q < 16; ++q) s += (q < cnt) ? vals[q] : 0.0;
         }
-        st_tagged(Gs + (size_t)e * 2, s, epoch);
+        st_tagged(Gs, E, e, s, epoch);
       }
     }
     const Src sr = slab_src(qc, qr);
@@ -322,8 +324,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       bool seen = tid >= NG;
       while (ok) {
         if (!seen) {
-          const unsigned long long* src = Gall + ((size_t)tid * E + ed) * 2;
-          const unsigned long long w0 = ld_u64(src), w1 = ld_u64(src + 1);
+          const unsigned long long* src = Gall + (size_t)tid * E * 2 + ed;
+          const unsigned long long w0 = ld_u64(src), w1 = ld_u64(src + E);
           seen = tag_ok(w0, w1, epoch);
         }
         if (__all(seen)) break;
@@ -346,9 +348,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         unsigned long long w0[16], w1[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          const unsigned long long* src = Gall + ((size_t)(q < NG ? q : NG - 1) * E + e) * 2;
+          const unsigned long long* src = Gall + (size_t)(q < NG ? q : NG - 1) * E * 2 + e;
           w0[q] = cached ? ld_u64_cached(src) : ld_u64(src);
-          w1[q] = cached ? ld_u64_cached(src + 1) : ld_u64(src + 1);
+          w1[q] = cached ? ld_u64_cached(src + E) : ld_u64(src + E);
         }
         cached = false;
 #pragma unroll
@@ -426,7 +428,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         if (q < nr) a0 += widen(col[q]) * z[q];
       }
       const double acc = group_sum(a0 + a1, tq);
-      if (c < nJ && sub == 0) st_tagged(P + (size_t)c * 2, acc, ep);
+      if (c < nJ && sub == 0) st_tagged(P, E, c, acc, ep);
     }
   };
   // partial error ||x - x_ref||^2 over owned columns (wave 0)
@@ -438,7 +440,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         e += d * d;
       }
       e = wave_sum(e);
-      if (tid == 0) st_tagged(P + (size_t)err_slot * 2, e, ep);
+      if (tid == 0) st_tagged(P, E, err_slot, e, ep);
     }
   };
 
@@ -495,7 +497,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         for (int cc = 0; cc < nc; ++cc) acc += widen(Sr[cc * nIk + l]) * x[cc];
         const int64_t gl = rI + l;
         if (gl >= r0 && gl < r1) acc += z[gl - r0] - bl[gl - r0];
-        st_tagged(P + (size_t)(MJ + l) * 2, acc, ep);
+        st_tagged(P, E, MJ + l, acc, ep);
       }
     }
     if (has_err) err_partial(P, ep);

@@ -47,8 +47,8 @@ struct SolveArgs {
 
 // Synchronisation workspace of the persistent grid kernel (zeroed before every launch).
 struct GridSync {
-  unsigned long long* part;  // 2 x grid x stride epoch-tagged pairs: per-workgroup partial vectors
-  unsigned long long* gsum;  // 32 x groups x stride epoch-tagged pairs: per-group sums (ring)
+  unsigned long long* part;  // 2 x grid vectors of stride epoch-tagged pairs (two planes of stride words)
+  unsigned long long* gsum;  // 32 x groups vectors of stride tagged pairs: per-group sums (ring)
   int* timeout;              // set when a wait exceeded its spin limit
   int32_t stride;            // entries per partial vector (>= max_nJ + max_nI + 1)
   int32_t groups;            // reduction groups (<= 16)
