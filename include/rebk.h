@@ -17,7 +17,7 @@
  *
  * with z^0 = b and x^0 = 0 in the paper's experiments (Section 3).  x^k
  * converges in mean square to A^+ b when z^0 is in b + range(A), x^0 is in
- * range(A^T) and 0 < alpha < 2 / beta_max (Theorem 5, Remark 9).
+ * range(A^T) and 0 < alpha < 2 / beta_max (Theorem 7, Remark 9).
  *
  * Conventions shared by every entry point:
  *  - Pointers named *_dev are device pointers (HIP global memory) owned by
@@ -148,7 +148,7 @@ void rebk_destroy(rebk_handle_t h);
  * Solve with the plain interface: z^0 = b, x^0 = x0_dev (NULL means 0), at
  * most max_iter iterations, residual stop rule
  *   ||b - z - A x|| <= tol ||b||  and  ||A^T z|| <= tol ||A||_F ||b||
- * checked every 256 iterations (z converges to (I - A A^+) b, Lemma 4, and
+ * checked every 256 iterations (z converges to (I - A A^+) b, Lemma 6, and
  * then A x converges to A A^+ b).  x_out_dev receives x (n entries).
  * res (host, may be NULL) receives the result.  Returns the solve status.
  */

@@ -1,18 +1,18 @@
 """Pins of the oracle's iteration against what the paper and linear algebra fix.
 
 * P1  limit A^+ b (Section 1, the four cases) from an SVD pseudoinverse on tiny systems;
-* P2  x^k - A^+ b stays in range(A^T) (proof of Theorem 5), so x^k in range(A^T) when x^0 = 0;
-* P3  z^k - b_perp stays in range(A) and z^k -> b_perp = (I - A A^+) b (Lemma 4);
+* P2  x^k - A^+ b stays in range(A^T) (proof of Theorem 7), so x^k in range(A^T) when x^0 = 0;
+* P3  z^k - b_perp stays in range(A) and z^k -> b_perp = (I - A A^+) b (Lemma 6);
 * P4  with one row block and one column block the iteration is deterministic and equals the
-      closed form of the proof of Theorem 1;
+      closed form of the proof of Theorem 2;
 * P5  for general partitions the mean of x^k over independent streams matches that closed form
-      (Theorem 1, expectation);
+      (Theorem 2, expectation);
 * P6  the block update is the weighted average of single-row/column projections (Section 2);
 * P7  s = m, t = n, alpha = 1 is REK (Section 2), checked against an independent REK loop;
       z^0 = 0 keeps z = 0 (Section 2);
 * P9  the x-trajectory does not depend on the component of b in null(A^T);
 * P10 scaling A and b by a power of two changes no block and no bit of x;
-* P11 Theorem 5 / Remark 9: the mean-square error stays below the stated bound.
+* P11 Theorem 7 / Remark 9: the mean-square error stays below the stated bound.
 """
 import numpy as np
 import pytest
@@ -86,7 +86,7 @@ def test_p3_z_converges_to_b_perp(oracle_lib):
 
 
 def closed_form_x(A, b, x0, z0, alpha, k):
-    """x^k from the expectation recursion in the proof of Theorem 1:
+    """x^k from the expectation recursion in the proof of Theorem 2:
     x^k - A^+ b = M^k (x^0 - A^+ b) - alpha k M^k A^T z^0 / ||A||_F^2, M = I - alpha A^T A / ||A||_F^2."""
     F2 = np.sum(A * A)
     n = A.shape[1]
@@ -113,7 +113,7 @@ def test_p4_single_block_closed_form(oracle_lib):
 
 
 def test_p5_expectation_matches_closed_form(oracle_lib):
-    """Theorem 1: E[x^k] follows the closed form for any partitions; 20000 independent streams."""
+    """Theorem 2: E[x^k] follows the closed form for any partitions; 20000 independent streams."""
     rng = np.random.default_rng(21)
     A = rng.standard_normal((8, 6))
     b = rng.standard_normal(8)
