@@ -125,9 +125,9 @@ typedef struct {
  * Philox seed (Algorithm 1).
  *
  * A is copied into library-owned device panels stored as panel_dtype:
- * every row block as an n x |I_i| column-major panel and every column block
- * as an m x |J_j| row-major panel, so that both block reads of an iteration
- * are contiguous.  A may be freed when the call returns.  The FP64 block
+ * every row block as an n x |I_i| column-major panel, and A^T row-major, so
+ * that column block j is |J_j| contiguous columns of m entries; both block
+ * reads of an iteration are contiguous.  A may be freed when the call returns.  The FP64 block
  * weights ||A_{I_i,:}||_F^2 and ||A_{:,J_j}||_F^2 of the stored values and the
  * sampling thresholds are computed here (the only host synchronisation).
  *
@@ -187,6 +187,92 @@ int rebk_sample_blocks(rebk_handle_t h, uint64_t system, int64_t k0, int64_t cou
  */
 int rebk_philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                        uint64_t k0, uint64_t k1, int64_t count, uint64_t *out_dev, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent systems, each with several right-hand
+ * sides, in one launch.  Every right-hand side is an exact REBK run
+ * (Algorithm 1) with z^0 = b and x^0 = x0 (or 0); the right-hand sides of
+ * one system share its block sequence, drawn from the Philox stream of the
+ * system's id (the counter's second word), so each panel read serves all
+ * of them.  Independent systems and right-hand sides are the units the
+ * method parallelises over without any exchange between them.
+ * ------------------------------------------------------------------------ */
+typedef struct rebk_batch *rebk_batch_t;
+
+/*
+ * Group nsys existing handles (created with the same panel_dtype and on the
+ * same device) into a batch.  sys_ids (host, nsys entries, may be NULL
+ * meaning 0, 1, ..., nsys-1) gives each system's Philox system id.  The
+ * batch refers to the handles' panels and tables: destroy the batch before
+ * any of its handles.  stream as in rebk_create.  Errors: REBK_ERR_INVALID
+ * (nsys < 1, a NULL handle, mixed panel types), REBK_ERR_OOM, REBK_ERR_HIP.
+ */
+int rebk_batch_create(rebk_batch_t *out, int32_t nsys, const rebk_handle_t *systems,
+                      const uint64_t *sys_ids, void *stream);
+
+/* Release the batch (not its handles; NULL is ignored). */
+void rebk_batch_destroy(rebk_batch_t b);
+
+/* Options of rebk_batch_solve and rebk_batch_autotune.  Zero-initialise. */
+typedef struct {
+    const int32_t *nrhs;            /* host, nsys entries: right-hand sides of system s (1..4096) */
+    const double *const *b_dev;     /* host array of nsys device pointers: nrhs[s] right-hand
+                                       sides of m_s entries each, one after another (required) */
+    const double *const *x0_dev;    /* NULL, or host array of nsys device pointers (entries may be
+                                       NULL meaning x0 = 0): nrhs[s] x n_s starting points */
+    const double *const *x_ref_dev; /* NULL, or host array of nsys device pointers: nrhs[s] x n_s
+                                       references (typically A^+ b); required for the stop rule */
+    double *const *x_out_dev;       /* host array of nsys device pointers: nrhs[s] x n_s results
+                                       (required) */
+    double *const *z_out_dev;       /* NULL, or host array of nsys device pointers: nrhs[s] x m_s */
+    int64_t max_iter;               /* iterations at most (> 0) */
+    double tol;                     /* a group of right-hand sides solved together stops at the
+                                       first check where every one of them has
+                                       ||x - x_ref|| / ||x_ref|| < tol; <= 0: run max_iter */
+    int64_t check_every;            /* check interval (0 means 16) */
+    int32_t threads;                /* threads per workgroup: 256 or 512 (0: tuned, else 512) */
+    int32_t lds_budget;             /* LDS bytes per workgroup for the iterates (0: tuned, else
+                                       the largest that fits) */
+    int32_t max_tile;               /* most right-hand sides per workgroup: 1, 2, 4 or 8
+                                       (0: tuned, else 8) */
+    int32_t xcd_order;              /* 1: dispatch the tasks of a system to one XCD (shared L2);
+                                       0: plain longest-first order; -1: tuned (default 1) */
+} rebk_batch_opts_t;
+
+/* Result of one right-hand side of a batch. */
+typedef struct {
+    int64_t iterations;  /* iterations run (shared by the right-hand sides solved together) */
+    double rel_err;      /* ||x - x_ref|| / ||x_ref|| at the last check, or -1 */
+    int32_t status;      /* REBK_OK, REBK_NOT_CONVERGED or REBK_DIVERGED */
+    int32_t tile;        /* right-hand sides solved together with this one */
+} rebk_batch_rhs_t;
+
+/*
+ * Solve every right-hand side of every system of the batch in one launch.
+ * Each workgroup takes up to max_tile right-hand sides of one system and
+ * keeps their iterates (m + n) x tile in LDS, so each system needs
+ * 8 (m + n) bytes plus a little under the LDS budget.  out (host,
+ * sum of nrhs entries, system after system) receives per right-hand side
+ * results; time_ms (host, may be NULL) the device time of the launch.
+ * Returns REBK_OK when every right-hand side stopped on the tolerance (or
+ * no stop rule was given), else REBK_NOT_CONVERGED or REBK_DIVERGED; errors
+ * REBK_ERR_INVALID (bad options, a system too large for LDS), REBK_ERR_OOM,
+ * REBK_ERR_HIP.  Synchronizes the stream.
+ */
+int rebk_batch_solve(rebk_batch_t b, const rebk_batch_opts_t *opts, rebk_batch_rhs_t *out,
+                     double *time_ms);
+
+/*
+ * Choose threads per workgroup, LDS budget, tile size and task order for
+ * this batch by timing probe_iters iterations (no stop rule) of each
+ * candidate on the given options (whose x_out buffers are overwritten).
+ * The choice is kept in the batch and used by later solves whose options
+ * leave those fields at 0 / -1; it is also returned (host pointers, may be
+ * NULL).  Synchronizes the stream.
+ */
+int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t *opts, int64_t probe_iters,
+                        int32_t *threads, int32_t *lds_budget, int32_t *max_tile, int32_t *xcd_order,
+                        double *best_ms);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *rebk_last_error(void);

@@ -15,7 +15,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "SolveResult", "philox4x64_10", "contiguous_offsets", "RebkError", "version"]
+__all__ = ["Solver", "SolveResult", "Batch", "philox4x64_10", "contiguous_offsets", "RebkError", "version"]
 
 RebkError = N.RebkError
 
@@ -187,6 +187,120 @@ class Solver:
         return SolveResult(status=N.STATUS_NAMES.get(res.status, str(res.status)), code=int(res.status),
                            kernel=N.KERNEL_NAMES.get(res.kernel, str(res.kernel)), iterations=int(res.iterations),
                            rel_err=float(res.rel_err), time_ms=float(res.time_ms))
+
+
+class Batch:
+    """``rebk_batch_create`` over existing solvers (same panel type): independent systems, each
+    with several right-hand sides, solved in one launch.  System s draws its blocks from the
+    Philox stream of ``sys_ids[s]`` (default s).  Close the batch before its solvers."""
+
+    def __init__(self, solvers: Sequence[Solver], sys_ids: Optional[Sequence[int]] = None):
+        lib = N.load()
+        self.solvers = list(solvers)
+        self.nsys = len(self.solvers)
+        hs = (ctypes.c_void_p * self.nsys)(*[sv._h.value for sv in self.solvers])
+        ids = None
+        if sys_ids is not None:
+            self._ids = (ctypes.c_uint64 * self.nsys)(*[int(v) for v in sys_ids])
+            ids = ctypes.cast(self._ids, ctypes.c_void_p)
+        b = ctypes.c_void_p()
+        N.check(lib.rebk_batch_create(ctypes.byref(b), self.nsys, ctypes.cast(hs, ctypes.c_void_p), ids,
+                                      _stream_ptr()), "rebk_batch_create")
+        self._b = b
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            N.load().rebk_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _opts(self, B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget, max_tile,
+              xcd_order):
+        """B[s]: (nrhs_s, m_s) float64 CUDA tensors; x_ref / x0 (optional) and x_out: (nrhs_s, n_s)."""
+        if len(B) != self.nsys:
+            raise ValueError("one right-hand-side matrix per system")
+        keep = []
+
+        def ptrs(lst, rows, cols_of, name, optional_entries=False):
+            if lst is None:
+                return None
+            arr = (ctypes.c_void_p * self.nsys)()
+            for s, t in enumerate(lst):
+                if t is None and optional_entries:
+                    arr[s] = None
+                    continue
+                shape = (rows[s], cols_of(s))
+                if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+                    raise ValueError(f"{name}[{s}] must be a contiguous CUDA float64 tensor of shape {shape}")
+                arr[s] = t.data_ptr()
+            keep.append(arr)
+            return ctypes.cast(arr, ctypes.c_void_p)
+
+        nrhs = [int(b.shape[0]) for b in B]
+        nr = (ctypes.c_int32 * self.nsys)(*nrhs)
+        keep.append(nr)
+        o = N.BatchOpts()
+        o.nrhs = ctypes.cast(nr, ctypes.c_void_p)
+        o.b_dev = ptrs(B, nrhs, lambda s: self.solvers[s].m, "B")
+        o.x0_dev = ptrs(x0, nrhs, lambda s: self.solvers[s].n, "x0", True)
+        o.x_ref_dev = ptrs(x_ref, nrhs, lambda s: self.solvers[s].n, "x_ref")
+        o.x_out_dev = ptrs(x_out, nrhs, lambda s: self.solvers[s].n, "x_out")
+        o.z_out_dev = ptrs(z_out, nrhs, lambda s: self.solvers[s].m, "z_out")
+        o.max_iter = int(max_iter)
+        o.tol = float(tol)
+        o.check_every = int(check_every)
+        o.threads = int(threads)
+        o.lds_budget = int(lds_budget)
+        o.max_tile = int(max_tile)
+        o.xcd_order = int(xcd_order)
+        return o, nrhs, keep
+
+    def solve(self, B, *, x_ref=None, x0=None, max_iter: int = 100000, tol: float = 0.0, check_every: int = 0,
+              threads: int = 0, lds_budget: int = 0, max_tile: int = 0, xcd_order: int = -1, want_z: bool = False):
+        """``rebk_batch_solve``.  Returns dict(x=[...], z=[...] or None, iterations, rel_err, status, tile
+        (numpy arrays over all right-hand sides, system after system), time_ms, code)."""
+        dev = self.solvers[0].device
+        x_out = [torch.empty((int(b.shape[0]), sv.n), dtype=torch.float64, device=dev)
+                 for b, sv in zip(B, self.solvers)]
+        z_out = ([torch.empty((int(b.shape[0]), sv.m), dtype=torch.float64, device=dev)
+                  for b, sv in zip(B, self.solvers)] if want_z else None)
+        o, nrhs, keep = self._opts(B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget,
+                                   max_tile, xcd_order)
+        total = sum(nrhs)
+        res = (N.BatchRhs * total)()
+        ms = ctypes.c_double(0.0)
+        code = N.load().rebk_batch_solve(self._b, ctypes.byref(o), ctypes.cast(res, ctypes.c_void_p),
+                                         ctypes.byref(ms))
+        N.check(code, "rebk_batch_solve")
+        del keep
+        return {
+            "x": x_out, "z": z_out, "code": code, "status": N.STATUS_NAMES.get(code, str(code)),
+            "time_ms": float(ms.value),
+            "iterations": np.array([r.iterations for r in res], dtype=np.int64),
+            "rel_err": np.array([r.rel_err for r in res]),
+            "rhs_status": np.array([r.status for r in res], dtype=np.int32),
+            "tile": np.array([r.tile for r in res], dtype=np.int32),
+        }
+
+    def autotune(self, B, *, x_ref=None, probe_iters: int = 64):
+        """``rebk_batch_autotune``: returns dict(threads, lds_budget, max_tile, xcd_order, ms)."""
+        dev = self.solvers[0].device
+        x_out = [torch.empty((int(b.shape[0]), sv.n), dtype=torch.float64, device=dev)
+                 for b, sv in zip(B, self.solvers)]
+        o, _, keep = self._opts(B, x_ref, None, x_out, None, probe_iters, 0.0, 0, 0, 0, 0, -1)
+        th, ld, tl, xo = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        N.check(N.load().rebk_batch_autotune(self._b, ctypes.byref(o), int(probe_iters), ctypes.byref(th),
+                                             ctypes.byref(ld), ctypes.byref(tl), ctypes.byref(xo), ctypes.byref(ms)),
+                "rebk_batch_autotune")
+        del keep
+        return {"threads": th.value, "lds_budget": ld.value, "max_tile": tl.value, "xcd_order": xo.value,
+                "ms": ms.value}
 
 
 def philox4x64_10(counter: Sequence[int], key: Sequence[int], count: int, device="cuda") -> torch.Tensor:

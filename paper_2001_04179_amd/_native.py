@@ -40,6 +40,18 @@ class SolveOpts(ctypes.Structure):
     ]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [
+        ("nrhs", P), ("b_dev", P), ("x0_dev", P), ("x_ref_dev", P), ("x_out_dev", P), ("z_out_dev", P),
+        ("max_iter", I64), ("tol", F64), ("check_every", I64), ("threads", I32), ("lds_budget", I32),
+        ("max_tile", I32), ("xcd_order", I32),
+    ]
+
+
+class BatchRhs(ctypes.Structure):
+    _fields_ = [("iterations", I64), ("rel_err", F64), ("status", I32), ("tile", I32)]
+
+
 # name -> (restype, argtypes); every function declared in include/rebk.h
 SIGNATURES = {
     "rebk_create": (ctypes.c_int, [ctypes.POINTER(P), P, I32, I32, I64, I64, I64, P, I64, P, I64, F64, U64, P]),
@@ -51,6 +63,12 @@ SIGNATURES = {
     "rebk_get_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 6),
     "rebk_sample_blocks": (ctypes.c_int, [P, U64, I64, I64, P, P]),
     "rebk_philox4x64_10": (ctypes.c_int, [U64, U64, U64, U64, U64, U64, I64, P, P]),
+    "rebk_batch_create": (ctypes.c_int, [ctypes.POINTER(P), I32, P, P, P]),
+    "rebk_batch_destroy": (None, [P]),
+    "rebk_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(BatchOpts), P, ctypes.POINTER(F64)]),
+    "rebk_batch_autotune": (ctypes.c_int, [P, ctypes.POINTER(BatchOpts), I64, ctypes.POINTER(I32),
+                                           ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                           ctypes.POINTER(F64)]),
     "rebk_last_error": (ctypes.c_char_p, []),
     "rebk_version": (ctypes.c_char_p, []),
 }

@@ -2,6 +2,8 @@
 // solve drivers behind the C ABI declared in include/rebk.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -577,6 +579,366 @@ int rebk_solve(rebk_handle_t h, const double* b_dev, const double* x0_dev, doubl
   o.x_out_dev = x_out_dev;
   o.kernel = REBK_KERNEL_AUTO;
   return rebk_solve_ex(h, &o, res);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched solves
+
+struct rebk_batch {
+  int32_t nsys = 0;
+  int panel_dtype = 0;
+  hipStream_t stream = nullptr;
+  int cus = 0;
+  int32_t max_nJ = 0, max_nI = 0;
+  std::vector<rebk_handle*> hs;
+  std::vector<int64_t> last_iters;  // per system, from the previous solve (longest-first order)
+  rebk::BatchSys* sys_d = nullptr;
+  // choices of rebk_batch_autotune (0 / -1: not tuned)
+  int32_t tuned_threads = 0, tuned_lds = 0, tuned_tile = 0, tuned_xcd = -1;
+  // launch buffers, grown as needed
+  rebk::BatchTask* tasks_d = nullptr;
+  int64_t* iters_d = nullptr;
+  int32_t* status_d = nullptr;
+  double* err2_d = nullptr;
+  double* xref2_d = nullptr;
+  size_t tasks_cap = 0, iters_cap = 0, status_cap = 0, err2_cap = 0, xref2_cap = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  ~rebk_batch() {
+    dfree(sys_d);
+    dfree(tasks_d);
+    dfree(iters_d);
+    dfree(status_d);
+    dfree(err2_d);
+    dfree(xref2_d);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+constexpr int kLdsMax = 160 * 1024 - 1024;  // per workgroup, leaving room for static shared memory
+
+struct BatchConfig {
+  int threads, lds_budget, max_tile, xcd_order;
+};
+
+BatchConfig batch_config(const rebk_batch* b, const rebk_batch_opts_t* o) {
+  BatchConfig c;
+  c.threads = o->threads ? o->threads : (b->tuned_threads ? b->tuned_threads : 512);
+  c.lds_budget = o->lds_budget ? o->lds_budget : (b->tuned_lds ? b->tuned_lds : kLdsMax);
+  c.max_tile = o->max_tile ? o->max_tile : (b->tuned_tile ? b->tuned_tile : 8);
+  c.xcd_order = o->xcd_order >= 0 ? o->xcd_order : (b->tuned_xcd >= 0 ? b->tuned_xcd : 1);
+  return c;
+}
+
+template <typename T>
+int grow(T*& p, size_t& cap, size_t need) {
+  if (need <= cap) return REBK_OK;
+  dfree(p);
+  if (hipMalloc((void**)&p, need * sizeof(T)) != hipSuccess) return fail(REBK_ERR_OOM, "cannot allocate %zu bytes", need * sizeof(T));
+  cap = need;
+  return REBK_OK;
+}
+
+// Run the batch once with configuration c.  Fills out (may be NULL) and *ms.
+int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, rebk_batch_rhs_t* out, double* ms,
+              int* overall) {
+  if (c.threads != 256 && c.threads != 512) return fail(REBK_ERR_INVALID, "threads must be 256 or 512");
+  if (c.max_tile != 1 && c.max_tile != 2 && c.max_tile != 4 && c.max_tile != 8)
+    return fail(REBK_ERR_INVALID, "max_tile must be 1, 2, 4 or 8");
+  if (c.lds_budget <= 0 || c.lds_budget > kLdsMax) return fail(REBK_ERR_INVALID, "lds_budget out of range");
+  const int32_t ns = b->nsys;
+  // tiles: per system the widest tile that fits the LDS budget, remainder in smaller tiles
+  struct Tile {
+    int32_t sys, rhs0, R;
+    int64_t rhs_index;  // global index of the tile's first right-hand side
+    double cost;
+  };
+  std::vector<Tile> tiles;
+  std::vector<int64_t> rhs_base(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) rhs_base[s + 1] = rhs_base[s] + o->nrhs[s];
+  size_t lds_max = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    const rebk_handle* h = b->hs[s];
+    int Rfit = 0;
+    for (int R = c.max_tile; R >= 1; R >>= 1)
+      if (rebk::batch_lds_bytes(h->m, h->n, R, b->max_nJ, b->max_nI, c.threads) <= (size_t)c.lds_budget) {
+        Rfit = R;
+        break;
+      }
+    if (Rfit == 0)
+      return fail(REBK_ERR_INVALID, "system %d (%lld x %lld) does not fit %d bytes of LDS", s, (long long)h->m,
+                  (long long)h->n, c.lds_budget);
+    const double per_iter = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
+    const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
+    int32_t done = 0;
+    while (done < o->nrhs[s]) {
+      int R = Rfit;
+      while (R > o->nrhs[s] - done) R >>= 1;
+      tiles.push_back({s, done, R, rhs_base[s] + done, per_iter * iters * (1.0 + 0.25 * R)});
+      const size_t lds = rebk::batch_lds_bytes(h->m, h->n, R, b->max_nJ, b->max_nI, c.threads);
+      if (lds > lds_max) lds_max = lds;
+      done += R;
+    }
+  }
+  // order: longest first; with xcd_order, whole systems go to the least loaded of the 8 XCDs and
+  // workgroup 8*slot + x runs slot `slot` of XCD x
+  std::vector<int32_t> order;  // tile index per workgroup, -1 for an empty slot
+  {
+    std::vector<int32_t> idx(tiles.size());
+    for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int32_t)q;
+    if (c.xcd_order) {
+      std::vector<double> sys_cost(ns, 0.0);
+      for (const Tile& t : tiles) sys_cost[t.sys] += t.cost;
+      std::vector<int32_t> sys_idx(ns);
+      for (int32_t s = 0; s < ns; ++s) sys_idx[s] = s;
+      std::stable_sort(sys_idx.begin(), sys_idx.end(), [&](int32_t p, int32_t q) { return sys_cost[p] > sys_cost[q]; });
+      std::vector<std::vector<int32_t>> lists(8);
+      std::vector<double> load(8, 0.0);
+      std::vector<std::vector<int32_t>> by_sys(ns);
+      for (size_t q = 0; q < tiles.size(); ++q) by_sys[tiles[q].sys].push_back((int32_t)q);
+      for (int32_t s : sys_idx) {
+        int best = 0;
+        for (int x = 1; x < 8; ++x)
+          if (load[x] < load[best]) best = x;
+        for (int32_t q : by_sys[s]) lists[best].push_back(q);
+        load[best] += sys_cost[s];
+      }
+      size_t slots = 0;
+      for (auto& l : lists) slots = l.size() > slots ? l.size() : slots;
+      order.assign(slots * 8, -1);
+      for (int x = 0; x < 8; ++x)
+        for (size_t q = 0; q < lists[x].size(); ++q) order[q * 8 + x] = lists[x][q];
+    } else {
+      std::stable_sort(idx.begin(), idx.end(), [&](int32_t p, int32_t q) { return tiles[p].cost > tiles[q].cost; });
+      order = idx;
+    }
+  }
+  const size_t ntask = order.size();
+  if (ntask > (size_t)INT32_MAX) return fail(REBK_ERR_INVALID, "too many tasks");
+  const size_t nrhs_total = (size_t)rhs_base[ns];
+  int rc = grow(b->tasks_d, b->tasks_cap, ntask);
+  if (rc == REBK_OK) rc = grow(b->iters_d, b->iters_cap, ntask);
+  if (rc == REBK_OK) rc = grow(b->status_d, b->status_cap, ntask);
+  if (rc == REBK_OK) rc = grow(b->err2_d, b->err2_cap, nrhs_total);
+  if (rc == REBK_OK) rc = grow(b->xref2_d, b->xref2_cap, nrhs_total);
+  if (rc != REBK_OK) return rc;
+  std::vector<rebk::BatchTask> tasks(ntask);
+  for (size_t w = 0; w < ntask; ++w) {
+    rebk::BatchTask& t = tasks[w];
+    t = rebk::BatchTask{};
+    t.sys = -1;
+    if (order[w] < 0) continue;
+    const Tile& tl = tiles[order[w]];
+    const rebk_handle* h = b->hs[tl.sys];
+    t.sys = tl.sys;
+    t.R = tl.R;
+    t.b = o->b_dev[tl.sys] + (int64_t)tl.rhs0 * h->m;
+    t.x_in = (o->x0_dev && o->x0_dev[tl.sys]) ? o->x0_dev[tl.sys] + (int64_t)tl.rhs0 * h->n : nullptr;
+    t.x_ref = o->x_ref_dev ? o->x_ref_dev[tl.sys] + (int64_t)tl.rhs0 * h->n : nullptr;
+    t.x_out = o->x_out_dev[tl.sys] + (int64_t)tl.rhs0 * h->n;
+    t.z_out = o->z_out_dev ? o->z_out_dev[tl.sys] + (int64_t)tl.rhs0 * h->m : nullptr;
+    t.iters_out = b->iters_d + w;
+    t.status_out = b->status_d + w;
+    t.err2_out = b->err2_d + tl.rhs_index;
+    t.xref2_out = b->xref2_d + tl.rhs_index;
+  }
+  rebk::BatchArgs a{};
+  a.sys = b->sys_d;
+  a.tasks = b->tasks_d;
+  a.ntasks = (int32_t)ntask;
+  a.max_nJ = b->max_nJ;
+  a.max_nI = b->max_nI;
+  a.max_iter = o->max_iter;
+  a.tol = o->tol;
+  a.check_every = o->check_every > 0 ? o->check_every : 16;
+  int per_cu = 0;
+  HIP_TRY(rebk::batch_max_blocks(b->panel_dtype, c.threads, lds_max, &per_cu));
+  if (per_cu <= 0) return fail(REBK_ERR_INVALID, "batch kernel cannot run with %zu bytes of LDS and %d threads", lds_max, c.threads);
+  hipStream_t st = b->stream;
+  HIP_TRY(hipMemcpyAsync(b->tasks_d, tasks.data(), ntask * sizeof(rebk::BatchTask), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(b->ev0, st));
+  HIP_TRY(rebk::launch_batch_solve(a, b->panel_dtype, c.threads, lds_max, st));
+  HIP_TRY(hipEventRecord(b->ev1, st));
+  std::vector<int64_t> it(ntask);
+  std::vector<int32_t> stt(ntask);
+  std::vector<double> e2(nrhs_total), x2(nrhs_total);
+  HIP_TRY(hipMemcpyAsync(it.data(), b->iters_d, ntask * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(stt.data(), b->status_d, ntask * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(e2.data(), b->err2_d, nrhs_total * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(x2.data(), b->xref2_d, nrhs_total * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float fms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&fms, b->ev0, b->ev1));
+  if (ms) *ms = fms;
+  int worst = REBK_OK;
+  std::vector<int64_t> sys_iters(ns, 0);
+  for (size_t w = 0; w < ntask; ++w) {
+    if (order[w] < 0) continue;
+    const Tile& tl = tiles[order[w]];
+    if (it[w] > sys_iters[tl.sys]) sys_iters[tl.sys] = it[w];
+    const int s_ = stt[w];
+    if (s_ == REBK_DIVERGED) worst = REBK_DIVERGED;
+    else if (s_ == REBK_NOT_CONVERGED && worst == REBK_OK) worst = REBK_NOT_CONVERGED;
+    if (out) {
+      for (int k = 0; k < tl.R; ++k) {
+        rebk_batch_rhs_t& r = out[tl.rhs_index + k];
+        r.iterations = it[w];
+        r.status = s_;
+        r.tile = tl.R;
+        const double ee = e2[tl.rhs_index + k], xx = x2[tl.rhs_index + k];
+        r.rel_err = (o->x_ref_dev && ee >= 0.0 && xx > 0.0) ? std::sqrt(ee) / std::sqrt(xx) : -1.0;
+      }
+    }
+  }
+  b->last_iters = sys_iters;
+  *overall = worst;
+  return REBK_OK;
+}
+
+int check_batch_opts(const rebk_batch* b, const rebk_batch_opts_t* o) {
+  if (!o) return fail(REBK_ERR_INVALID, "opts is NULL");
+  if (!o->nrhs || !o->b_dev || !o->x_out_dev) return fail(REBK_ERR_INVALID, "nrhs, b and x_out are required");
+  if (o->max_iter <= 0) return fail(REBK_ERR_INVALID, "max_iter must be positive");
+  if (o->check_every < 0) return fail(REBK_ERR_INVALID, "check_every must be non-negative");
+  if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
+  if (o->tol > 0.0 && !o->x_ref_dev) return fail(REBK_ERR_INVALID, "a tolerance needs x_ref");
+  for (int32_t s = 0; s < b->nsys; ++s) {
+    if (o->nrhs[s] < 1 || o->nrhs[s] > 4096) return fail(REBK_ERR_INVALID, "nrhs[%d] must be in 1..4096", s);
+    if (!o->b_dev[s] || !o->x_out_dev[s]) return fail(REBK_ERR_INVALID, "b and x_out of system %d are NULL", s);
+    if (o->x_ref_dev && !o->x_ref_dev[s]) return fail(REBK_ERR_INVALID, "x_ref of system %d is NULL", s);
+    if (o->z_out_dev && !o->z_out_dev[s]) return fail(REBK_ERR_INVALID, "z_out of system %d is NULL", s);
+  }
+  return REBK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rebk_batch_create(rebk_batch_t* out, int32_t nsys, const rebk_handle_t* systems, const uint64_t* sys_ids,
+                      void* stream) {
+  g_err[0] = 0;
+  if (!out) return fail(REBK_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (nsys < 1 || !systems) return fail(REBK_ERR_INVALID, "need at least one system");
+  for (int32_t s = 0; s < nsys; ++s) {
+    if (!systems[s]) return fail(REBK_ERR_INVALID, "system %d is NULL", s);
+    if (systems[s]->panel_dtype != systems[0]->panel_dtype) return fail(REBK_ERR_INVALID, "mixed panel types");
+    if (systems[s]->device != systems[0]->device) return fail(REBK_ERR_INVALID, "systems on different devices");
+  }
+  rebk_batch* b = new (std::nothrow) rebk_batch();
+  if (!b) return fail(REBK_ERR_OOM, "host allocation failed");
+  b->nsys = nsys;
+  b->panel_dtype = systems[0]->panel_dtype;
+  b->stream = (hipStream_t)stream;
+  b->cus = systems[0]->cus;
+  b->hs.assign(systems, systems + nsys);
+  b->last_iters.assign(nsys, 0);
+  std::vector<rebk::BatchSys> S(nsys);
+  for (int32_t s = 0; s < nsys; ++s) {
+    const rebk_handle* h = systems[s];
+    rebk::BatchSys& d = S[s];
+    d.Arow = h->Arow;
+    d.Acol = h->Acol;
+    d.row_off = h->row_off_d;
+    d.col_off = h->col_off_d;
+    d.T_row = h->T_row;
+    d.T_col = h->T_col;
+    d.coef_row = h->coef_row;
+    d.coef_col = h->coef_col;
+    d.m = h->m;
+    d.n = h->n;
+    d.s = (int32_t)h->s;
+    d.t = (int32_t)h->t;
+    d.max_nI = h->max_nI;
+    d.max_nJ = h->max_nJ;
+    d.seed = h->seed;
+    d.sys = sys_ids ? sys_ids[s] : (uint64_t)s;
+    if (h->max_nJ > b->max_nJ) b->max_nJ = h->max_nJ;
+    if (h->max_nI > b->max_nI) b->max_nI = h->max_nI;
+  }
+  auto bail = [&](int code) {
+    delete b;
+    return code;
+  };
+  if (hipMalloc((void**)&b->sys_d, nsys * sizeof(rebk::BatchSys)) != hipSuccess)
+    return bail(fail(REBK_ERR_OOM, "cannot allocate the system table"));
+  hipError_t e = hipMemcpyAsync(b->sys_d, S.data(), nsys * sizeof(rebk::BatchSys), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e != hipSuccess) return bail(fail(REBK_ERR_HIP, "batch setup: %s", hipGetErrorString(e)));
+  *out = b;
+  return REBK_OK;
+}
+
+void rebk_batch_destroy(rebk_batch_t b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+}
+
+int rebk_batch_solve(rebk_batch_t b, const rebk_batch_opts_t* o, rebk_batch_rhs_t* out, double* time_ms) {
+  g_err[0] = 0;
+  if (!b) return fail(REBK_ERR_INVALID, "batch is NULL");
+  int rc = check_batch_opts(b, o);
+  if (rc != REBK_OK) return rc;
+  double ms = 0.0;
+  int overall = REBK_OK;
+  rc = batch_run(b, o, batch_config(b, o), out, &ms, &overall);
+  if (rc != REBK_OK) return rc;
+  if (time_ms) *time_ms = ms;
+  return overall;
+}
+
+int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t* o, int64_t probe_iters, int32_t* threads,
+                        int32_t* lds_budget, int32_t* max_tile, int32_t* xcd_order, double* best_ms) {
+  g_err[0] = 0;
+  if (!b) return fail(REBK_ERR_INVALID, "batch is NULL");
+  int rc = check_batch_opts(b, o);
+  if (rc != REBK_OK) return rc;
+  if (probe_iters <= 0) return fail(REBK_ERR_INVALID, "probe_iters must be positive");
+  rebk_batch_opts_t p = *o;
+  p.max_iter = probe_iters;
+  p.tol = 0.0;
+  const int cand_threads[] = {256, 512};
+  const int cand_tile[] = {1, 4, 8};
+  const int cand_lds[] = {kLdsMax, 80 * 1024 - 512};
+  BatchConfig best{0, 0, 0, 1};
+  double best_t = 1e300;
+  for (int xo = 1; xo >= 0; --xo)
+    for (int th : cand_threads)
+      for (int tl : cand_tile)
+        for (int ld : cand_lds) {
+          BatchConfig c{th, ld, tl, xo};
+          double ms = 0.0;
+          int overall = 0;
+          const std::vector<int64_t> keep = b->last_iters;
+          int r = batch_run(b, &p, c, nullptr, &ms, &overall);
+          b->last_iters = keep;
+          if (r == REBK_ERR_INVALID) continue;  // this candidate does not fit
+          if (r != REBK_OK) return r;
+          if (ms < best_t) {
+            best_t = ms;
+            best = c;
+          }
+        }
+  if (best.threads == 0) return fail(REBK_ERR_INVALID, "no configuration fits the batch");
+  g_err[0] = 0;
+  b->tuned_threads = best.threads;
+  b->tuned_lds = best.lds_budget;
+  b->tuned_tile = best.max_tile;
+  b->tuned_xcd = best.xcd_order;
+  if (threads) *threads = best.threads;
+  if (lds_budget) *lds_budget = best.lds_budget;
+  if (max_tile) *max_tile = best.max_tile;
+  if (xcd_order) *xcd_order = best.xcd_order;
+  if (best_ms) *best_ms = best_t;
+  return REBK_OK;
 }
 
 }  // extern "C"

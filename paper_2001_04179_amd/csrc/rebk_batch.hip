@@ -1,0 +1,317 @@
+// Batched REBK for gfx950: many independent systems, many right-hand sides, one launch
+// (Du, Si, Sun, arXiv:2001.04179, Algorithm 1 applied to each system and right-hand side).
+//
+// Every workgroup runs one task: R right-hand sides of one system, from start to stop.  All
+// right-hand sides of a system share its block sequence (the Philox counter carries the system
+// id, not the right-hand side), so one read of a panel element feeds R accumulators: the block
+// products become small GEMMs, A_{:,J}^T Z and A_{I,:} X with R columns.  The iterates Z (m x R)
+// and X (n x R) stay in LDS for the whole task, stored right-hand side after right-hand side so
+// that consecutive lanes touch consecutive words.  The host orders the tasks so that the tasks of
+// one system are dispatched to the same XCD (workgroup b goes to XCD b mod 8); they walk the same
+// panels at about the same pace and share them through that XCD's L2.
+//
+// The iterates are FP64 and the panels any of FP64/FP32/BF16/FP16, widened exactly.  The
+// contractions run as FP64 FMAs on the vector units: on this chip FP64 matrix cores have the same
+// peak as the vector units, and a narrower type for the iterates would not reach the tolerances
+// the method is run to.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rebk_device.h"
+#include "rebk_internal.h"
+
+namespace rebk {
+namespace {
+
+using namespace dev;
+
+template <int CTRL>
+__device__ __forceinline__ double bdpp(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+// Sum over aligned groups of `width` lanes (power of two <= 64); every lane of a group gets the
+// group's sum.  All 64 lanes must execute it.
+__device__ __forceinline__ double lane_group_sum(double v, int width) {
+  if (width >= 2) v += bdpp<0xB1>(v);    // quad_perm [1,0,3,2]
+  if (width >= 4) v += bdpp<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (width >= 8) v += bdpp<0x141>(v);   // row_half_mirror
+  if (width >= 16) v += bdpp<0x140>(v);  // row_mirror
+  if (width >= 32) v += __shfl_xor(v, 16, 64);
+  if (width >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ __forceinline__ int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+constexpr int kDrawBatch = 64;  // block draws computed at a time
+
+struct BatchLayout {
+  size_t z, x, v, u, ew, total;  // offsets in doubles
+};
+
+__host__ __device__ inline BatchLayout batch_layout(int64_t m, int64_t n, int R, int max_nJ, int max_nI,
+                                                    int threads) {
+  BatchLayout L;
+  L.z = 0;
+  L.x = L.z + (size_t)R * m;
+  L.v = L.x + (size_t)R * n;
+  L.u = L.v + (size_t)R * max_nJ;
+  L.ew = L.u + (size_t)R * max_nI;
+  L.total = L.ew + (size_t)R * ((threads + 63) / 64) + 2 * (size_t)R;
+  return L;
+}
+
+template <typename TP, int R>
+__device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs& a, double* lds, int* s_j,
+                         int* s_i) {
+  const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = (T + 63) >> 6;
+  const int64_t m = S.m, n = S.n;
+  const BatchLayout L = batch_layout(m, n, R, a.max_nJ, a.max_nI, T);
+  double* z = lds + L.z;    // z[k * m + r]
+  double* x = lds + L.x;    // x[k * n + c]
+  double* v = lds + L.v;    // v[k * max_nJ + c]
+  double* u = lds + L.u;    // u[k * max_nI + l]
+  double* ew = lds + L.ew;  // per-wave partial errors, then R totals and R reference norms
+  double* etot = ew + (size_t)R * nw;
+  double* xr2 = etot + R;
+  const int MJ = a.max_nJ, MI = a.max_nI;
+  const TP* __restrict__ Arow = (const TP*)S.Arow;
+  const TP* __restrict__ Acol = (const TP*)S.Acol;
+
+  for (int64_t e = tid; e < (int64_t)R * m; e += T) z[e] = tk.b[e];
+  for (int64_t e = tid; e < (int64_t)R * n; e += T) x[e] = tk.x_in ? tk.x_in[e] : 0.0;
+
+  const bool checking = tk.x_ref != nullptr;
+  const bool stopping = checking && a.tol > 0.0;
+  const int64_t ce = a.check_every > 0 ? a.check_every : 1;
+
+  // Per right-hand side sum over c < n of f(k, c), reduced in a fixed order; results in out[k].
+  auto colwise_sum = [&](auto f, double* out) {
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    for (int64_t c = tid; c < n; c += T) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] += f(k, c);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const double s = lane_group_sum(acc[k], 64);
+      if (lane == 0) ew[wid * R + k] = s;
+    }
+    __syncthreads();
+    if (tid < R) {
+      double s = 0.0;
+      for (int q = 0; q < nw; ++q) s += ew[q * R + tid];
+      out[tid] = s;
+    }
+    __syncthreads();
+  };
+  if (checking) {
+    colwise_sum([&](int k, int64_t c) { const double r = tk.x_ref[k * n + c]; return r * r; }, xr2);
+    if (tid < R) tk.xref2_out[tid] = xr2[tid];
+  }
+
+  int status = 1;
+  int64_t done = 0;
+  for (int64_t q = 0; q < a.max_iter; ++q) {
+    const int64_t k1 = q + 1;  // 1-based iteration number
+    if ((q % kDrawBatch) == 0) {
+      __syncthreads();
+      if (tid < kDrawBatch && q + tid < a.max_iter) {
+        int jj, ii;
+        draw_pair(S, k1 + tid, jj, ii);
+        s_j[tid] = jj;
+        s_i[tid] = ii;
+      }
+      __syncthreads();
+    }
+    const int j = s_j[q % kDrawBatch], i = s_i[q % kDrawBatch];
+
+    // ---- z-phase: V = A_{:,J}^T Z (nJ x R), G lanes per column sum strided rows
+    const int64_t c0 = S.col_off[j];
+    const int nJ = (int)(S.col_off[j + 1] - c0);
+    const TP* __restrict__ P = Acol + m * c0;  // (r, c) at c * m + r
+    {
+      int G = T / pow2_at_least(nJ);
+      if (G > 64) G = 64;
+      if (G < 1) G = 1;
+      const int per = T / G;
+      for (int cb = 0; cb < nJ; cb += per) {
+        const int c = cb + tid / G, g = tid % G;
+        double acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0.0;
+        if (c < nJ) {
+          const TP* col = P + (int64_t)c * m;
+#pragma unroll 2
+          for (int64_t r = g; r < m; r += G) {
+            const double av = widen(col[r]);
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += av * z[k * m + r];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = lane_group_sum(acc[k], G);
+        if (c < nJ && g == 0) {
+#pragma unroll
+          for (int k = 0; k < R; ++k) v[k * MJ + c] = acc[k];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- z update: Z -= coef_J * A_{:,J} V, one thread per row
+    {
+      const double cc = S.coef_col[j];
+      for (int64_t r = tid; r < m; r += T) {
+        double acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0.0;
+        for (int c = 0; c < nJ; ++c) {
+          const double av = widen(P[(int64_t)c * m + r]);
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] += av * v[k * MJ + c];
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) z[k * m + r] -= cc * acc[k];
+      }
+    }
+    __syncthreads();
+    // ---- x-phase: U = A_{I,:} X - B_I + Z_I (nI x R), G lanes per row sum strided columns
+    const int64_t r0 = S.row_off[i];
+    const int nI = (int)(S.row_off[i + 1] - r0);
+    const TP* __restrict__ Q = Arow + n * r0;  // (l, c) at c * nI + l
+    {
+      int G = T / pow2_at_least(nI);
+      if (G > 64) G = 64;
+      if (G < 1) G = 1;
+      const int per = T / G;
+      for (int lb = 0; lb < nI; lb += per) {
+        const int l = lb + tid / G, g = tid % G;
+        double acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0.0;
+        if (l < nI) {
+#pragma unroll 2
+          for (int64_t c = g; c < n; c += G) {
+            const double av = widen(Q[c * nI + l]);
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += av * x[k * n + c];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = lane_group_sum(acc[k], G);
+        if (l < nI && g == 0) {
+#pragma unroll
+          for (int k = 0; k < R; ++k) u[k * MI + l] = (acc[k] - tk.b[k * m + r0 + l]) + z[k * m + r0 + l];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- x update: X -= coef_I * A_{I,:}^T U, 8 lanes per column
+    {
+      const double cr = S.coef_row[i];
+      constexpr int W = 8;
+      const int per = T / W;
+      for (int64_t cb = 0; cb < n; cb += per) {
+        const int64_t c = cb + tid / W;
+        const int sub = tid % W;
+        double acc[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = 0.0;
+        if (c < n) {
+          const TP* col = Q + c * nI;
+          for (int l = sub; l < nI; l += W) {
+            const double av = widen(col[l]);
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += av * u[k * MI + l];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] = lane_group_sum(acc[k], W);
+        if (c < n && sub == 0) {
+#pragma unroll
+          for (int k = 0; k < R; ++k) x[k * n + c] -= cr * acc[k];
+        }
+      }
+    }
+    __syncthreads();
+    done = k1;
+
+    // ---- stop rule: every right-hand side below tol relative to its reference
+    if (checking && (k1 % ce == 0 || k1 == a.max_iter)) {
+      colwise_sum([&](int k, int64_t c) { const double d = x[k * n + c] - tk.x_ref[k * n + c]; return d * d; }, etot);
+      bool all_ok = true, bad = false;
+      for (int k = 0; k < R; ++k) {
+        const double rel = sqrt(etot[k]) / (xr2[k] > 0.0 ? sqrt(xr2[k]) : 1.0);  // absolute if x_ref = 0
+        all_ok = all_ok && rel < a.tol;
+        bad = bad || !isfinite(etot[k]) || rel > 1e6;
+      }
+      if (stopping && all_ok) { status = 0; break; }
+      if (bad) { status = 2; break; }
+    }
+  }
+
+  for (int64_t e = tid; e < (int64_t)R * n; e += T) tk.x_out[e] = x[e];
+  if (tk.z_out)
+    for (int64_t e = tid; e < (int64_t)R * m; e += T) tk.z_out[e] = z[e];
+  if (tid < R) tk.err2_out[tid] = checking ? etot[tid] : -1.0;
+  if (tid == 0) {
+    if (!stopping && status == 1) status = checking ? 1 : 0;
+    *tk.iters_out = done;
+    *tk.status_out = status;
+  }
+}
+
+template <typename TP>
+__global__ void __launch_bounds__(512) batch_solve_kernel(BatchArgs a) {
+  extern __shared__ double lds[];
+  __shared__ int s_j[kDrawBatch], s_i[kDrawBatch];
+  if ((int)blockIdx.x >= a.ntasks) return;
+  const BatchTask tk = a.tasks[blockIdx.x];
+  if (tk.sys < 0) return;
+  const BatchSys S = a.sys[tk.sys];
+  switch (tk.R) {
+    case 1: run_task<TP, 1>(S, tk, a, lds, s_j, s_i); break;
+    case 2: run_task<TP, 2>(S, tk, a, lds, s_j, s_i); break;
+    case 4: run_task<TP, 4>(S, tk, a, lds, s_j, s_i); break;
+    case 8: run_task<TP, 8>(S, tk, a, lds, s_j, s_i); break;
+    default: break;
+  }
+}
+
+}  // namespace
+
+size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads) {
+  return batch_layout(m, n, R, max_nJ, max_nI, threads).total * sizeof(double);
+}
+
+hipError_t batch_max_blocks(int panel_dtype, int threads, size_t lds_bytes, int* blocks_per_cu) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    hipError_t e = hipFuncSetAttribute((const void*)batch_solve_kernel<TP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)batch_solve_kernel<TP>, threads,
+                                                        lds_bytes);
+  });
+}
+
+hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    hipError_t e = hipFuncSetAttribute((const void*)batch_solve_kernel<TP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batch_solve_kernel<TP>), dim3(a.ntasks), dim3(threads), lds_bytes, st, a);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace rebk

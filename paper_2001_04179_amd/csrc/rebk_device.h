@@ -65,7 +65,8 @@ __device__ __forceinline__ int draw_block(const uint64_t* __restrict__ T, int nb
 
 // Blocks (j, i) of iteration k (1-based): counter (k-1, sys, 0, 0), key (seed, 0); word 0 draws
 // the column block, word 1 the row block.
-__device__ __forceinline__ void draw_pair(const SolveArgs& a, int64_t k, int& j, int& i) {
+template <typename Args>
+__device__ __forceinline__ void draw_pair(const Args& a, int64_t k, int& j, int& i) {
   uint64_t c0 = (uint64_t)(k - 1), c1 = a.sys, c2 = 0, c3 = 0;
   philox4x64_10(c0, c1, c2, c3, a.seed, 0);
   j = draw_block(a.T_col, a.t, c0);

@@ -54,6 +54,48 @@ struct GridSync {
   int32_t groups;            // reduction groups (<= 16)
 };
 
+// One system of a batch: its panels, tables and Philox stream (device copy of the handle's data).
+struct BatchSys {
+  const void* Arow;          // row panels, as in SolveArgs
+  const void* Acol;          // column panels (A^T row-major), as in SolveArgs
+  const int64_t* row_off;
+  const int64_t* col_off;
+  const uint64_t* T_row;
+  const uint64_t* T_col;
+  const double* coef_row;
+  const double* coef_col;
+  int64_t m, n;
+  int32_t s, t;
+  int32_t max_nI, max_nJ;
+  uint64_t seed, sys;
+};
+
+// The work of one workgroup: R right-hand sides of one system, solved together (they share the
+// block sequence, so every panel element read serves all R of them).
+struct BatchTask {
+  int32_t sys;               // index into the BatchSys array; -1: empty slot
+  int32_t R;                 // right-hand sides: 1, 2, 4 or 8
+  const double* b;           // R vectors of length m, one after another
+  const double* x_in;        // R vectors of length n, or NULL (x0 = 0)
+  const double* x_ref;       // R vectors of length n, or NULL (no error check)
+  double* x_out;             // R vectors of length n
+  double* z_out;             // R vectors of length m, or NULL
+  int64_t* iters_out;        // one value: iterations run
+  double* err2_out;          // R values: ||x - x_ref||^2 at the last check (-1 if none)
+  double* xref2_out;         // R values: ||x_ref||^2
+  int32_t* status_out;       // one value: 0 stopped on tol, 1 max_iter reached, 2 diverged
+};
+
+struct BatchArgs {
+  const BatchSys* sys;
+  const BatchTask* tasks;
+  int32_t ntasks;
+  int32_t max_nJ, max_nI;    // over the batch (LDS layout)
+  int64_t max_iter;
+  double tol;                // relative tolerance per right-hand side (<= 0: none)
+  int64_t check_every;
+};
+
 // Launchers (defined in rebk_kernels.hip).  All return hipError_t.
 hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype, int64_t m, int64_t n,
                        const int64_t* row_off_d, const int64_t* col_off_d, const int32_t* rowblk_d,
@@ -76,6 +118,9 @@ size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype);
 hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, const SolveArgs& a,
                            const double* x, const double* z, double* partials, int nparts, hipStream_t st);
+size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads);
+hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st);
+hipError_t batch_max_blocks(int panel_dtype, int threads, size_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_err2(const double* x, const double* x_ref, int64_t n, double* partials, int nparts,
                        hipStream_t st);
 

@@ -166,6 +166,121 @@ def rank1500_20000x2000(rng_seed=1002, seed=0, scale: int = 1) -> System:
                           fro2_target=float(m))
 
 
+@dataclass
+class BatchSystem:
+    """One system of a batch with several right-hand sides (rows of B, X_ref)."""
+    A: np.ndarray            # m x n
+    B: np.ndarray            # nrhs x m
+    X_star: np.ndarray       # nrhs x n
+    X_ref: np.ndarray        # nrhs x n, A^+ b for every right-hand side
+    row_off: np.ndarray
+    col_off: np.ndarray
+    alpha: float
+    sys_id: int
+    rank: int
+    beta_row: float = 0.0
+    beta_col: float = 0.0
+
+    @property
+    def shape(self):
+        return self.A.shape
+
+
+def _spd_solve(G: np.ndarray, R: np.ndarray) -> np.ndarray:
+    from scipy.linalg import cho_factor, cho_solve
+    return cho_solve(cho_factor(G, lower=False, check_finite=False), R, check_finite=False)
+
+
+def batch_system(m: int, n: int, rank: Optional[int], nrhs: int, rng: np.random.Generator, *, noise=0.05,
+                 row_tau=64, col_tau=16, alpha_c=1.0, sys_id=0) -> BatchSystem:
+    """Dense N(0, 1) A (m x n) or, with ``rank``, the factor product U V / sqrt(rank) (U m x rank,
+    V rank x n, N(0, 1)).  Right-hand sides b = A x* + r, x* ~ N(0, I), r = (I - P_range(A)) g
+    scaled to ||r|| = noise ||A x*|| (r = 0 where null(A^T) = {0}); x_ref = P_range(A^T) x*.
+    The projections use Cholesky factors of the Gram matrices of full-rank factors, so a system of
+    a few thousand rows and columns is built in a fraction of a second."""
+    X = rng.standard_normal((nrhs, n))
+    if rank is None:
+        A = rng.standard_normal((m, n))
+        if m >= n:          # full column rank: range(A^T) = R^n, x_ref = x*
+            AX = X @ A.T
+            Gm = rng.standard_normal((nrhs, m))
+            Rn = Gm - (_spd_solve(A.T @ A, (Gm @ A).T).T @ A.T)
+            X_ref = X.copy()
+        else:               # full row rank: null(A^T) = {0}, consistent; x_ref = A^T (A A^T)^-1 A x*
+            AX = X @ A.T
+            Rn = np.zeros((nrhs, m))
+            X_ref = _spd_solve(A @ A.T, AX.T).T @ A
+        r_rank = min(m, n)
+    else:
+        U = rng.standard_normal((m, rank))
+        V = rng.standard_normal((rank, n))
+        A = (U @ V) / np.sqrt(rank)
+        AX = X @ A.T
+        Gm = rng.standard_normal((nrhs, m))
+        Rn = Gm - (_spd_solve(U.T @ U, (Gm @ U).T).T @ U.T)     # (I - U (U^T U)^-1 U^T) g
+        X_ref = _spd_solve(V @ V.T, (X @ V.T).T).T @ V           # V^T (V V^T)^-1 V x*
+        r_rank = rank
+    B = AX.copy()
+    for k in range(nrhs):
+        rn = np.linalg.norm(Rn[k])
+        if noise > 0.0 and rn > 0.0:
+            B[k] += Rn[k] * (noise * np.linalg.norm(AX[k]) / rn)
+    ro = contiguous_offsets(m, row_tau)
+    co = contiguous_offsets(n, col_tau)
+    br, bc = beta_max(A, ro, co)
+    return BatchSystem(A=np.ascontiguousarray(A), B=np.ascontiguousarray(B), X_star=X,
+                       X_ref=np.ascontiguousarray(X_ref), row_off=ro, col_off=co, alpha=alpha_c / max(br, bc),
+                       sys_id=sys_id, rank=r_rank, beta_row=br, beta_col=bc)
+
+
+def batch_shapes(count: int, rng: np.random.Generator, m_range=(500, 8000), n_range=(100, 2000),
+                 min_aspect=4.0, rank_every=4):
+    """Shapes of a batch: m, n uniform in their ranges, redrawn until max/min >= min_aspect (a
+    near-square Gaussian system is so ill-conditioned that the method needs millions of
+    iterations); odd-indexed systems are transposed (m < n, half the batch underdetermined); every
+    rank_every-th system (index rank_every-1, 2 rank_every-1, ...) has rank floor(min(m, n) / 2)."""
+    shapes = []
+    while len(shapes) < count:
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        if max(m, n) < min_aspect * min(m, n):
+            continue
+        idx = len(shapes)
+        if idx % 2 == 1:
+            m, n = n, m
+        rank = min(m, n) // 2 if (rank_every and idx % rank_every == rank_every - 1) else None
+        shapes.append((m, n, rank))
+    return shapes
+
+
+def batch_256_dense(rng_seed=1004, count=256, nrhs=16, m_range=(500, 8000), n_range=(100, 2000), min_aspect=4.0,
+                    noise=0.05, row_tau=64, col_tau=16, workers=1):
+    """The batched workload: 256 dense Gaussian systems with m in [500, 8000] and n in [100, 2000]
+    (aspect ratio at least 4, odd ones transposed, every fourth of rank min(m, n)/2), 16
+    right-hand sides each with noise ratio 0.05, blocks of 64 rows and 16 columns, alpha =
+    1 / beta_max per system, Philox system id = index, seed 0.  ``workers`` > 1 builds the
+    systems in that many processes (same values)."""
+    shapes = batch_shapes(count, np.random.default_rng(rng_seed), m_range, n_range, min_aspect)
+    args = [(rng_seed, q, m, n, rk, nrhs, noise, row_tau, col_tau) for q, (m, n, rk) in enumerate(shapes)]
+    # one BLAS thread per system whatever the worker count; workers are threads: the random fills and BLAS calls release the GIL and nothing is copied
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        if workers > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=workers) as ex:
+                return list(ex.map(_batch_member, args))
+        return [_batch_member(a) for a in args]
+
+
+def _batch_member(args) -> BatchSystem:
+    """System q of a batch, from its own generator seeded with (rng_seed, q): any subset of a batch
+    can be rebuilt, in any order or in parallel (random values identical, BLAS-computed ones equal
+    up to rounding)."""
+    rng_seed, q, m, n, rk, nrhs, noise, row_tau, col_tau = args
+    rng = np.random.default_rng([rng_seed, q])
+    return batch_system(m, n, rk, nrhs, rng, noise=noise, row_tau=row_tau, col_tau=col_tau, sys_id=q)
+
+
 def round_to_bf16(A: np.ndarray) -> np.ndarray:
     """Round FP64 values to the nearest bfloat16 (ties to even), returned as FP64.
 
