@@ -52,6 +52,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-iters", type=int, default=2000)
     p.add_argument("--scale", type=int, default=1, help="divide the problem dimensions (quick checks only)")
+    p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched"],
+                   help="rank1500: the 20000 x 2000 single system; batched: 256 systems x 16 right-hand sides")
+    p.add_argument("--batch-panels", default="f32", choices=["f64", "f32", "bf16", "f16"])
+    p.add_argument("--batch-count", type=int, default=256)
+    p.add_argument("--batch-plain-sample", type=int, default=8,
+                   help="systems whose first right-hand side is also solved alone with FP64 panels")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", TRAFFIC_FILE),
@@ -143,6 +149,143 @@ def cpu_baseline(S, iters_to_tol, sample_iters):
     }
 
 
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
+
+
+def bench_batched(args):
+    """256 independent dense systems x 16 right-hand sides, one batched launch per step, to
+    relative error 1e-6 for every right-hand side (checked every 16 iterations)."""
+    import torch
+    import paper_2001_04179_amd as rebk
+    from paper_2001_04179_amd import workloads as W
+    stored = {"f64": None, "f32": W.round_to_f32, "bf16": W.round_to_bf16, "f16": W.round_to_f16}[args.batch_panels]
+    t0 = time.perf_counter()
+    systems = W.batch_256_dense(count=args.batch_count, workers=16)
+    t_gen = time.perf_counter() - t0
+    print(f"# generated {len(systems)} systems in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    solvers = []
+    t0 = time.perf_counter()
+    for S in systems:
+        A_d = torch.from_numpy(S.A).to(dev)
+        solvers.append(rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, 0, panel_dtype=args.batch_panels))
+        del A_d
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    batch = rebk.Batch(solvers, sys_ids=[S.sys_id for S in systems])
+    B = [torch.from_numpy(S.B).to(dev) for S in systems]
+    XR = [torch.from_numpy(S.X_ref).to(dev) for S in systems]
+    t0 = time.perf_counter()
+    tuned = batch.autotune(B, x_ref=XR, probe_iters=32)
+    t_tune = time.perf_counter() - t0
+    print(f"# create {t_create:.1f} s, autotune {t_tune:.1f} s: {tuned}", file=sys.stderr, flush=True)
+
+    def one():
+        return batch.solve(B, x_ref=XR, max_iter=2_000_000, tol=args.tol, check_every=16)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [one() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = outs[-1]
+    nrhs_total = int(sum(S.B.shape[0] for S in systems))
+    # true error against A^+ b of every right-hand side
+    errs = []
+    for s, S in enumerate(systems):
+        X = out["x"][s].cpu().numpy()
+        for k in range(S.B.shape[0]):
+            errs.append(float(np.linalg.norm(X[k] - S.X_ref[k]) / np.linalg.norm(S.X_ref[k])))
+    kernel_ms = float(np.mean([o["time_ms"] for o in outs]))
+    # algorithmic panel bytes: each system-iteration reads its two blocks once (shared by the
+    # right-hand sides solved together through L2); flops: 4 (m |J| + |I| n) per right-hand side
+    esz = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.batch_panels]
+    bytes_alg = 0.0
+    flops = 0.0
+    q = 0
+    for s, S in enumerate(systems):
+        m, n = S.A.shape
+        per = (m * (n / (len(S.col_off) - 1)) + (m / (len(S.row_off) - 1)) * n)  # mean elements per iteration
+        its = out["iterations"][q:q + S.B.shape[0]]
+        bytes_alg += esz * per * float(np.max(its))
+        flops += 4.0 * per * float(np.sum(its))
+        q += S.B.shape[0]
+    gbs = bytes_alg / (kernel_ms * 1e-3) / 1e9
+    tflops = flops / (kernel_ms * 1e-3) / 1e12
+    # plain FP64 REBK on the same inputs, one right-hand side at a time (sampled systems)
+    plain = []
+    pick = list(range(0, len(systems), max(1, len(systems) // max(1, args.batch_plain_sample))))[:args.batch_plain_sample]
+    for sidx in pick:
+        S = systems[sidx]
+        A_d = torch.from_numpy(S.A).to(dev)
+        sv = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, 0, panel_dtype="f64")
+        del A_d
+        t1 = time.perf_counter()
+        o = sv.solve_ex(B[sidx][0].contiguous(), x_ref=XR[sidx][0].contiguous(), tol=args.tol, check_every=1,
+                        max_iter=2_000_000)
+        torch.cuda.synchronize()
+        plain.append({"system": sidx, "shape": list(S.A.shape), "seconds": time.perf_counter() - t1,
+                      "iterations": o["result"].iterations, "kernel": o["result"].kernel, "status": o["result"].status})
+        sv.close()
+    plain_total_est = float(np.mean([p["seconds"] for p in plain])) * nrhs_total
+    value = nrhs_total / (wall / args.steps)
+    line = {
+        "metric": "time & iters to rel err 1e-6 (solves/s, GB/s vs roofline), chosen form vs plain REBK",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(systems)} dense systems (m, n in [500, 8000] x [100, 2000], aspect >= 4, "
+                               f"odd ones transposed, every 4th rank min/2) x 16 right-hand sides, blocks 64 x 16, "
+                               f"tol {args.tol:g}", "panel_dtype": args.batch_panels, "systems": len(systems),
+                   "rhs_total": nrhs_total, "tuned": tuned},
+        "status": out["status"],
+        "iterations": {"min": int(out["iterations"].min()), "median": float(np.median(out["iterations"])),
+                       "max": int(out["iterations"].max()), "sum": int(out["iterations"].sum())},
+        "rel_err_max": float(max(errs)),
+        "kernel_ms": kernel_ms,
+        "speedup_vs_plain_f64_est": plain_total_est / (wall / args.steps),
+        "plain_f64_sample": plain,
+        "prep_seconds": {"generate": t_gen, "create": t_create, "autotune": t_tune},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "batch_solve_kernel",
+                     "fp64_tflops": tflops, "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+                     "fp64_frac": tflops / FP64_PEAK_TFLOPS},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # the oracle on the first right-hand side of a few systems, 400 iterations each, scaled to
+        # the iterations the batch ran
+        t_sum, it_sum = 0.0, 0
+        for sidx in pick[:4]:
+            S = systems[sidx]
+            t1 = time.perf_counter()
+            oracle.rebk_solve(stored(S.A) if stored else S.A, S.row_off, S.col_off, S.alpha, 0, S.B[0], max_iter=400,
+                              sys=S.sys_id, trace=False)
+            t_sum += time.perf_counter() - t1
+            it_sum += 400
+        # seconds per iteration of a system, averaged over the sample, times all right-hand-side iterations
+        per_it = t_sum / it_sum
+        total = per_it * float(out["iterations"].sum())
+        line["cpu_baseline"] = {"value": nrhs_total / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": f"FP64 C oracle, single thread: 400 iterations of the first right-hand side "
+                                          f"of systems {pick[:4]}, {per_it * 1e3:.3f} ms/iteration, scaled to the "
+                                          f"{int(out['iterations'].sum())} right-hand-side iterations of the batch"}
+    batch.close()
+    for sv in solvers:
+        sv.close()
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -151,6 +294,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
     import torch
     import paper_2001_04179_amd as rebk
     from paper_2001_04179_amd import workloads as W

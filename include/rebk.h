@@ -233,8 +233,8 @@ typedef struct {
     int32_t threads;                /* threads per workgroup: 256 or 512 (0: tuned, else 512) */
     int32_t lds_budget;             /* LDS bytes per workgroup for the iterates (0: tuned, else
                                        the largest that fits) */
-    int32_t max_tile;               /* most right-hand sides per workgroup: 1, 2, 4 or 8
-                                       (0: tuned, else 8) */
+    int32_t max_tile;               /* most right-hand sides per workgroup: 1, 2 or 4
+                                       (0: tuned, else 4) */
     int32_t xcd_order;              /* 1: dispatch the tasks of a system to one XCD (shared L2);
                                        0: plain longest-first order; -1: tuned (default 1) */
 } rebk_batch_opts_t;

@@ -72,6 +72,7 @@ void dfree(T*& p) {
 
 struct rebk_handle {
   int64_t m = 0, n = 0, s = 0, t = 0;
+  int64_t ldc = 0;  // column-panel stride (m rounded up)
   int32_t max_nI = 0, max_nJ = 0;
   int panel_dtype = 0;
   double alpha = 0.0;
@@ -169,6 +170,7 @@ rebk::SolveArgs base_args(const rebk_handle* h) {
   a.coef_col = h->coef_col;
   a.m = h->m;
   a.n = h->n;
+  a.ldc = h->ldc;
   a.s = (int32_t)h->s;
   a.t = (int32_t)h->t;
   a.max_nI = h->max_nI;
@@ -300,8 +302,9 @@ int rebk_create(rebk_handle_t* out, const void* A_dev, int32_t a_dtype, int32_t 
 
   const size_t esz = dtype_size(panel_dtype);
   const size_t elems = (size_t)m * (size_t)n;
+  h->ldc = rebk::col_stride(m);
   ALLOC_H(h->Arow, elems * esz);
-  ALLOC_H(h->Acol, elems * esz);
+  ALLOC_H(h->Acol, (size_t)h->ldc * (size_t)n * esz);
   ALLOC_H(h->row_off_d, (s + 1) * sizeof(int64_t));
   ALLOC_H(h->col_off_d, (t + 1) * sizeof(int64_t));
   ALLOC_H(h->T_row, s * sizeof(uint64_t));
@@ -357,9 +360,10 @@ int rebk_create(rebk_handle_t* out, const void* A_dev, int32_t a_dtype, int32_t 
   TRY_S(hipMemcpyAsync(h->col_off_d, h->col_off.data(), (t + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   TRY_S(hipMemsetAsync(bad_d, 0, sizeof(int), st));
   TRY_S(rebk::launch_finite_check(A_dev, a_dtype, lda, m, n, bad_d, st));
-  TRY_S(rebk::launch_pack(A_dev, a_dtype, lda, panel_dtype, m, n, h->row_off_d, h->col_off_d, rowblk_d, colblk_d,
-                          h->Arow, h->Acol, st));
-  TRY_S(rebk::launch_block_weights(h->Arow, h->Acol, panel_dtype, m, n, h->row_off_d, (int32_t)s, h->col_off_d,
+  if (h->ldc > m) TRY_S(hipMemsetAsync(h->Acol, 0, (size_t)h->ldc * (size_t)n * esz, st));  // zero pad entries
+  TRY_S(rebk::launch_pack(A_dev, a_dtype, lda, panel_dtype, m, n, h->ldc, h->row_off_d, h->col_off_d, rowblk_d,
+                          colblk_d, h->Arow, h->Acol, st));
+  TRY_S(rebk::launch_block_weights(h->Arow, h->Acol, panel_dtype, m, n, h->ldc, h->row_off_d, (int32_t)s, h->col_off_d,
                                    (int32_t)t, rowblk_d, row_sq, colrow_sq, w_d, w_d + s, st));
   std::vector<double> w(s + t);
   int bad = 0;
@@ -629,7 +633,7 @@ BatchConfig batch_config(const rebk_batch* b, const rebk_batch_opts_t* o) {
   BatchConfig c;
   c.threads = o->threads ? o->threads : (b->tuned_threads ? b->tuned_threads : 512);
   c.lds_budget = o->lds_budget ? o->lds_budget : (b->tuned_lds ? b->tuned_lds : kLdsMax);
-  c.max_tile = o->max_tile ? o->max_tile : (b->tuned_tile ? b->tuned_tile : 8);
+  c.max_tile = o->max_tile ? o->max_tile : (b->tuned_tile ? b->tuned_tile : 4);
   c.xcd_order = o->xcd_order >= 0 ? o->xcd_order : (b->tuned_xcd >= 0 ? b->tuned_xcd : 1);
   return c;
 }
@@ -647,8 +651,7 @@ int grow(T*& p, size_t& cap, size_t need) {
 int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, rebk_batch_rhs_t* out, double* ms,
               int* overall) {
   if (c.threads != 256 && c.threads != 512) return fail(REBK_ERR_INVALID, "threads must be 256 or 512");
-  if (c.max_tile != 1 && c.max_tile != 2 && c.max_tile != 4 && c.max_tile != 8)
-    return fail(REBK_ERR_INVALID, "max_tile must be 1, 2, 4 or 8");
+  if (c.max_tile != 1 && c.max_tile != 2 && c.max_tile != 4) return fail(REBK_ERR_INVALID, "max_tile must be 1, 2 or 4");
   if (c.lds_budget <= 0 || c.lds_budget > kLdsMax) return fail(REBK_ERR_INVALID, "lds_budget out of range");
   const int32_t ns = b->nsys;
   // tiles: per system the widest tile that fits the LDS budget, remainder in smaller tiles
@@ -852,6 +855,7 @@ int rebk_batch_create(rebk_batch_t* out, int32_t nsys, const rebk_handle_t* syst
     d.coef_col = h->coef_col;
     d.m = h->m;
     d.n = h->n;
+    d.ldc = h->ldc;
     d.s = (int32_t)h->s;
     d.t = (int32_t)h->t;
     d.max_nI = h->max_nI;
@@ -906,7 +910,7 @@ int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t* o, int64_t prob
   p.max_iter = probe_iters;
   p.tol = 0.0;
   const int cand_threads[] = {256, 512};
-  const int cand_tile[] = {1, 4, 8};
+  const int cand_tile[] = {1, 2, 4};
   const int cand_lds[] = {kLdsMax, 80 * 1024 - 512};
   BatchConfig best{0, 0, 0, 1};
   double best_t = 1e300;

@@ -43,6 +43,62 @@ __device__ __forceinline__ double lane_group_sum(double v, int width) {
   return v;
 }
 
+// Pointers read from the task table are generic; the compiler would access them with flat
+// instructions, which also count on the LDS wait counter, so every LDS read of the iterates would
+// wait for all panel loads in flight.  These casts state that they point to global memory.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const GLOBAL_AS T* gptr(const T* p) {
+  return (const GLOBAL_AS T*)p;
+}
+template <typename T>
+__device__ __forceinline__ GLOBAL_AS T* gptr(T* p) {
+  return (GLOBAL_AS T*)p;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// Four consecutive panel entries (a chunk aligned to 4 entries) held in their stored type until
+// they are used, so a thread can keep many chunks in flight: one 16-byte load for FP32, two for
+// FP64, one 8-byte load for the 2-byte types.  get(i) widens entry i exactly to FP64.
+template <typename TP>
+struct Chunk4;
+template <>
+struct Chunk4<float> {
+  f32x4 v;
+  __device__ __forceinline__ void load(const GLOBAL_AS float* p) { v = *(const GLOBAL_AS f32x4*)p; }
+  __device__ __forceinline__ double get(int i) const { return (double)v[i]; }
+};
+template <>
+struct Chunk4<double> {
+  f64x2 a, b;
+  __device__ __forceinline__ void load(const GLOBAL_AS double* p) {
+    a = *(const GLOBAL_AS f64x2*)p;
+    b = *(const GLOBAL_AS f64x2*)(p + 2);
+  }
+  __device__ __forceinline__ double get(int i) const { return i < 2 ? a[i] : b[i - 2]; }
+};
+template <>
+struct Chunk4<__bf16> {
+  u32x2 v;  // entry 0 in the low half of the first word
+  __device__ __forceinline__ void load(const GLOBAL_AS __bf16* p) { v = *(const GLOBAL_AS u32x2*)p; }
+  __device__ __forceinline__ double get(int i) const {
+    const unsigned w = v[i >> 1];
+    return (double)__uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+  }
+};
+template <>
+struct Chunk4<_Float16> {
+  u32x2 v;
+  __device__ __forceinline__ void load(const GLOBAL_AS _Float16* p) { v = *(const GLOBAL_AS u32x2*)p; }
+  __device__ __forceinline__ double get(int i) const {
+    const unsigned w = v[i >> 1];
+    return (double)(float)__builtin_bit_cast(_Float16, (unsigned short)((i & 1) ? (w >> 16) : (w & 0xffffu)));
+  }
+};
+
 __device__ __forceinline__ int pow2_at_least(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -50,6 +106,16 @@ __device__ __forceinline__ int pow2_at_least(int x) {
 }
 
 constexpr int kDrawBatch = 64;  // block draws computed at a time
+// panel loads a thread issues before it consumes them: more for narrow tiles, whose accumulators
+// leave registers free
+template <int R>
+constexpr int unroll_for() { return R >= 8 ? 2 : (R >= 4 ? 4 : 8); }
+// 4-entry vector loads in flight: phases whose accumulators are R values per lane, and phases
+// that keep 4 R accumulators (four rows at once)
+template <int R>
+constexpr int vec_unroll_light() { return R >= 2 ? 8 : 16; }
+template <int R>
+constexpr int vec_unroll_heavy() { return R >= 2 ? 4 : 8; }
 
 struct BatchLayout {
   size_t z, x, v, u, ew, total;  // offsets in doubles
@@ -81,11 +147,23 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
   double* etot = ew + (size_t)R * nw;
   double* xr2 = etot + R;
   const int MJ = a.max_nJ, MI = a.max_nI;
-  const TP* __restrict__ Arow = (const TP*)S.Arow;
-  const TP* __restrict__ Acol = (const TP*)S.Acol;
+  const GLOBAL_AS TP* __restrict__ Arow = gptr((const TP*)S.Arow);
+  const GLOBAL_AS TP* __restrict__ Acol = gptr((const TP*)S.Acol);
+  const GLOBAL_AS int64_t* __restrict__ col_off = gptr(S.col_off);
+  const GLOBAL_AS int64_t* __restrict__ row_off = gptr(S.row_off);
+  const GLOBAL_AS double* __restrict__ coef_col = gptr(S.coef_col);
+  const GLOBAL_AS double* __restrict__ coef_row = gptr(S.coef_row);
+  const GLOBAL_AS double* __restrict__ bvec = gptr(tk.b);
+  const GLOBAL_AS double* __restrict__ xref = gptr(tk.x_ref);
+  constexpr int kUnroll = unroll_for<R>();
 
-  for (int64_t e = tid; e < (int64_t)R * m; e += T) z[e] = tk.b[e];
-  for (int64_t e = tid; e < (int64_t)R * n; e += T) x[e] = tk.x_in ? tk.x_in[e] : 0.0;
+  for (int64_t e = tid; e < (int64_t)R * m; e += T) z[e] = bvec[e];
+  if (tk.x_in) {
+    const GLOBAL_AS double* x0 = gptr(tk.x_in);
+    for (int64_t e = tid; e < (int64_t)R * n; e += T) x[e] = x0[e];
+  } else {
+    for (int64_t e = tid; e < (int64_t)R * n; e += T) x[e] = 0.0;
+  }
 
   const bool checking = tk.x_ref != nullptr;
   const bool stopping = checking && a.tol > 0.0;
@@ -114,7 +192,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     __syncthreads();
   };
   if (checking) {
-    colwise_sum([&](int k, int64_t c) { const double r = tk.x_ref[k * n + c]; return r * r; }, xr2);
+    colwise_sum([&](int k, int64_t c) { const double r = xref[k * n + c]; return r * r; }, xr2);
     if (tid < R) tk.xref2_out[tid] = xr2[tid];
   }
 
@@ -134,11 +212,15 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     }
     const int j = s_j[q % kDrawBatch], i = s_i[q % kDrawBatch];
 
-    // ---- z-phase: V = A_{:,J}^T Z (nJ x R), G lanes per column sum strided rows
-    const int64_t c0 = S.col_off[j];
-    const int nJ = (int)(S.col_off[j + 1] - c0);
-    const TP* __restrict__ P = Acol + m * c0;  // (r, c) at c * m + r
-    {
+    // ---- z-phase: V = A_{:,J}^T Z (nJ x R).  Column runs start at multiples of 16 entries and
+    // are zero-padded to ldc, so every lane reads whole aligned 4-row chunks: G lanes per column,
+    // chunks g, g + G, ...; rows past m hold 0 in the panel and read a valid z row.
+    const int64_t c0 = col_off[j];
+    const int nJ = (int)(col_off[j + 1] - c0);
+    const int64_t ldc = S.ldc;
+    const GLOBAL_AS TP* __restrict__ P = Acol + ldc * c0;  // (r, c) at c * ldc + r
+    if constexpr (R >= 4) {
+      // wide tiles: one panel entry per load (the 4-row form would not fit in registers)
       int G = T / pow2_at_least(nJ);
       if (G > 64) G = 64;
       if (G < 1) G = 1;
@@ -149,12 +231,22 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = 0.0;
         if (c < nJ) {
-          const TP* col = P + (int64_t)c * m;
-#pragma unroll 2
-          for (int64_t r = g; r < m; r += G) {
-            const double av = widen(col[r]);
+          const GLOBAL_AS TP* col = P + (int64_t)c * ldc;
+          for (int64_t r = g; r < m; r += (int64_t)G * kUnroll) {
+            double av[kUnroll];
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += av * z[k * m + r];
+            for (int e = 0; e < kUnroll; ++e) {
+              const int64_t rr = r + (int64_t)e * G;
+              const double w = widen(col[rr < m ? rr : m - 1]);
+              av[e] = rr < m ? w : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < kUnroll; ++e) {
+              const int64_t rr = r + (int64_t)e * G;
+              const int64_t rc = rr < m ? rr : m - 1;
+#pragma unroll
+              for (int k = 0; k < R; ++k) acc[k] += av[e] * z[k * m + rc];
+            }
           }
         }
 #pragma unroll
@@ -164,30 +256,175 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
           for (int k = 0; k < R; ++k) v[k * MJ + c] = acc[k];
         }
       }
-    }
-    __syncthreads();
-    // ---- z update: Z -= coef_J * A_{:,J} V, one thread per row
-    {
-      const double cc = S.coef_col[j];
+      __syncthreads();
+      const double cc = coef_col[j];
       for (int64_t r = tid; r < m; r += T) {
         double acc[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = 0.0;
-        for (int c = 0; c < nJ; ++c) {
-          const double av = widen(P[(int64_t)c * m + r]);
+        for (int cb2 = 0; cb2 < nJ; cb2 += kUnroll) {
+          double av[kUnroll];
 #pragma unroll
-          for (int k = 0; k < R; ++k) acc[k] += av * v[k * MJ + c];
+          for (int e = 0; e < kUnroll; ++e) {
+            const int ce_ = cb2 + e < nJ ? cb2 + e : nJ - 1;
+            const double w = widen(P[(int64_t)ce_ * ldc + r]);
+            av[e] = cb2 + e < nJ ? w : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < kUnroll; ++e) {
+            const int ce_ = cb2 + e < nJ ? cb2 + e : nJ - 1;
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += av[e] * v[k * MJ + ce_];
+          }
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) z[k * m + r] -= cc * acc[k];
       }
+      __syncthreads();
+    } else {
+    const int64_t nq = (m + 3) >> 2;
+      {
+        constexpr int U = vec_unroll_light<R>();
+        int G = T / pow2_at_least(nJ);
+        if (G > 64) G = 64;
+        if (G < 1) G = 1;
+        const int per = T / G;
+        for (int cb = 0; cb < nJ; cb += per) {
+          const int c = cb + tid / G, g = tid % G;
+          double acc[R];
+  #pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = 0.0;
+          if (c < nJ) {
+            const GLOBAL_AS TP* col = P + (int64_t)c * ldc;
+            for (int64_t q0 = g; q0 < nq; q0 += (int64_t)G * U) {
+              Chunk4<TP> ch[U];
+  #pragma unroll
+              for (int e = 0; e < U; ++e) {  // clamped chunk: no branch around the load
+                const int64_t qe = q0 + (int64_t)e * G;
+                ch[e].load(col + 4 * (qe < nq ? qe : nq - 1));
+              }
+  #pragma unroll
+              for (int e = 0; e < U; ++e) {
+                const int64_t qe = q0 + (int64_t)e * G;
+                const int64_t qc = qe < nq ? qe : nq - 1;
+                const double on = qe < nq ? 1.0 : 0.0;
+  #pragma unroll
+                for (int i4 = 0; i4 < 4; ++i4) {
+                  const int64_t row = 4 * qc + i4 < m ? 4 * qc + i4 : m - 1;
+                  const double av = on * ch[e].get(i4);
+  #pragma unroll
+                  for (int k = 0; k < R; ++k) acc[k] += av * z[k * m + row];
+                }
+              }
+            }
+          }
+  #pragma unroll
+          for (int k = 0; k < R; ++k) acc[k] = lane_group_sum(acc[k], G);
+          if (c < nJ && g == 0) {
+  #pragma unroll
+            for (int k = 0; k < R; ++k) v[k * MJ + c] = acc[k];
+          }
+        }
+      }
+      __syncthreads();
+      // ---- z update: Z -= coef_J * A_{:,J} V, one thread per 4-row chunk
+      {
+        constexpr int U = vec_unroll_heavy<R>();
+        const double cc = coef_col[j];
+        for (int64_t qq = tid; qq < nq; qq += T) {
+          double acc[4][R];
+  #pragma unroll
+          for (int i4 = 0; i4 < 4; ++i4)
+  #pragma unroll
+            for (int k = 0; k < R; ++k) acc[i4][k] = 0.0;
+          for (int cb2 = 0; cb2 < nJ; cb2 += U) {
+            Chunk4<TP> ch[U];
+  #pragma unroll
+            for (int e = 0; e < U; ++e) {
+              const int ce_ = cb2 + e < nJ ? cb2 + e : nJ - 1;
+              ch[e].load(P + (int64_t)ce_ * ldc + 4 * qq);
+            }
+  #pragma unroll
+            for (int e = 0; e < U; ++e) {
+              const int ce_ = cb2 + e < nJ ? cb2 + e : nJ - 1;
+              const double on = cb2 + e < nJ ? 1.0 : 0.0;
+  #pragma unroll
+              for (int i4 = 0; i4 < 4; ++i4) {
+                const double av = on * ch[e].get(i4);
+  #pragma unroll
+                for (int k = 0; k < R; ++k) acc[i4][k] += av * v[k * MJ + ce_];
+              }
+            }
+          }
+  #pragma unroll
+          for (int i4 = 0; i4 < 4; ++i4) {
+            const int64_t row = 4 * qq + i4;
+            if (row < m) {
+  #pragma unroll
+              for (int k = 0; k < R; ++k) z[k * m + row] -= cc * acc[i4][k];
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     // ---- x-phase: U = A_{I,:} X - B_I + Z_I (nI x R), G lanes per row sum strided columns
-    const int64_t r0 = S.row_off[i];
-    const int nI = (int)(S.row_off[i + 1] - r0);
-    const TP* __restrict__ Q = Arow + n * r0;  // (l, c) at c * nI + l
-    {
+    const int64_t r0 = row_off[i];
+    const int nI = (int)(row_off[i + 1] - r0);
+    const GLOBAL_AS TP* __restrict__ Q = Arow + n * r0;  // (l, c) at c * nI + l
+    // whole aligned 4-row chunks in every column of the block (all blocks but a ragged last one)
+    const bool vrow = R <= 2 && (nI & 3) == 0 && ((n * r0) & 3) == 0;
+    const int nqI = nI >> 2;
+    if (vrow) {
+      constexpr int U = vec_unroll_heavy<R>();
+      int G = T / pow2_at_least(nqI);
+      if (G > 64) G = 64;
+      if (G < 1) G = 1;
+      const int per = T / G;
+      for (int lb = 0; lb < nqI; lb += per) {
+        const int lq = lb + tid / G, g = tid % G;
+        double acc[4][R];
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4)
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[i4][k] = 0.0;
+        if (lq < nqI) {
+          for (int64_t c = g; c < n; c += (int64_t)G * U) {
+            Chunk4<TP> ch[U];
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+              const int64_t ce_ = c + (int64_t)e * G;
+              ch[e].load(Q + (ce_ < n ? ce_ : n - 1) * nI + 4 * lq);
+            }
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+              const int64_t ce_ = c + (int64_t)e * G;
+              const int64_t cl = ce_ < n ? ce_ : n - 1;
+              const double on = ce_ < n ? 1.0 : 0.0;
+#pragma unroll
+              for (int k = 0; k < R; ++k) {
+                const double xv = on * x[k * n + cl];
+#pragma unroll
+                for (int i4 = 0; i4 < 4; ++i4) acc[i4][k] += ch[e].get(i4) * xv;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int i4 = 0; i4 < 4; ++i4)
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[i4][k] = lane_group_sum(acc[i4][k], G);
+        if (lq < nqI && g == 0) {
+#pragma unroll
+          for (int i4 = 0; i4 < 4; ++i4) {
+            const int l = 4 * lq + i4;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+              u[k * MI + l] = (acc[i4][k] - bvec[k * m + r0 + l]) + z[k * m + r0 + l];
+          }
+        }
+      }
+    } else {
       int G = T / pow2_at_least(nI);
       if (G > 64) G = 64;
       if (G < 1) G = 1;
@@ -198,25 +435,78 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = 0.0;
         if (l < nI) {
-#pragma unroll 2
-          for (int64_t c = g; c < n; c += G) {
-            const double av = widen(Q[c * nI + l]);
+          for (int64_t c = g; c < n; c += (int64_t)G * kUnroll) {
+            double av[kUnroll];
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += av * x[k * n + c];
+            for (int e = 0; e < kUnroll; ++e) {
+              const int64_t cc = c + (int64_t)e * G;
+              const double w = widen(Q[(cc < n ? cc : n - 1) * nI + l]);
+              av[e] = cc < n ? w : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < kUnroll; ++e) {
+              const int64_t cc = c + (int64_t)e * G;
+              const int64_t ccl = cc < n ? cc : n - 1;
+#pragma unroll
+              for (int k = 0; k < R; ++k) acc[k] += av[e] * x[k * n + ccl];
+            }
           }
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = lane_group_sum(acc[k], G);
         if (l < nI && g == 0) {
 #pragma unroll
-          for (int k = 0; k < R; ++k) u[k * MI + l] = (acc[k] - tk.b[k * m + r0 + l]) + z[k * m + r0 + l];
+          for (int k = 0; k < R; ++k) u[k * MI + l] = (acc[k] - bvec[k * m + r0 + l]) + z[k * m + r0 + l];
         }
       }
     }
     __syncthreads();
-    // ---- x update: X -= coef_I * A_{I,:}^T U, 8 lanes per column
-    {
-      const double cr = S.coef_row[i];
+    // ---- x update: X -= coef_I * A_{I,:}^T U
+    if (vrow) {
+      // W lanes per column, one 4-row chunk each; every thread handles U columns at once
+      constexpr int U = vec_unroll_light<R>();
+      const double cr = coef_row[i];
+      int W = pow2_at_least(nqI);
+      if (W > 64) W = 64;
+      const int per = T / W;
+      const int sub = tid % W;
+      for (int64_t cb = 0; cb < n; cb += (int64_t)per * U) {
+        double acc[U][R];
+#pragma unroll
+        for (int e = 0; e < U; ++e)
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[e][k] = 0.0;
+        for (int lq = sub; lq < nqI; lq += W) {
+          Chunk4<TP> ch[U];
+#pragma unroll
+          for (int e = 0; e < U; ++e) {
+            const int64_t c = cb + tid / W + (int64_t)e * per;
+            ch[e].load(Q + (c < n ? c : n - 1) * nI + 4 * lq);
+          }
+#pragma unroll
+          for (int e = 0; e < U; ++e)
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+#pragma unroll
+              for (int i4 = 0; i4 < 4; ++i4) acc[e][k] += ch[e].get(i4) * u[k * MI + 4 * lq + i4];
+        }
+#pragma unroll
+        for (int e = 0; e < U; ++e)
+#pragma unroll
+          for (int k = 0; k < R; ++k) acc[e][k] = lane_group_sum(acc[e][k], W);
+        if (sub == 0) {
+#pragma unroll
+          for (int e = 0; e < U; ++e) {
+            const int64_t c = cb + tid / W + (int64_t)e * per;
+            if (c < n) {
+#pragma unroll
+              for (int k = 0; k < R; ++k) x[k * n + c] -= cr * acc[e][k];
+            }
+          }
+        }
+      }
+    } else {
+      const double cr = coef_row[i];
       constexpr int W = 8;
       const int per = T / W;
       for (int64_t cb = 0; cb < n; cb += per) {
@@ -226,11 +516,21 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
 #pragma unroll
         for (int k = 0; k < R; ++k) acc[k] = 0.0;
         if (c < n) {
-          const TP* col = Q + c * nI;
-          for (int l = sub; l < nI; l += W) {
-            const double av = widen(col[l]);
+          const GLOBAL_AS TP* col = Q + c * nI;
+          for (int l0 = sub; l0 < nI; l0 += W * kUnroll) {
+            double av[kUnroll];
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += av * u[k * MI + l];
+            for (int e = 0; e < kUnroll; ++e) {
+              const int le = l0 + e * W < nI ? l0 + e * W : nI - 1;
+              const double w = widen(col[le]);
+              av[e] = l0 + e * W < nI ? w : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < kUnroll; ++e) {
+              const int le = l0 + e * W < nI ? l0 + e * W : nI - 1;
+#pragma unroll
+              for (int k = 0; k < R; ++k) acc[k] += av[e] * u[k * MI + le];
+            }
           }
         }
 #pragma unroll
@@ -246,7 +546,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
 
     // ---- stop rule: every right-hand side below tol relative to its reference
     if (checking && (k1 % ce == 0 || k1 == a.max_iter)) {
-      colwise_sum([&](int k, int64_t c) { const double d = x[k * n + c] - tk.x_ref[k * n + c]; return d * d; }, etot);
+      colwise_sum([&](int k, int64_t c) { const double d = x[k * n + c] - xref[k * n + c]; return d * d; }, etot);
       bool all_ok = true, bad = false;
       for (int k = 0; k < R; ++k) {
         const double rel = sqrt(etot[k]) / (xr2[k] > 0.0 ? sqrt(xr2[k]) : 1.0);  // absolute if x_ref = 0
@@ -258,9 +558,14 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     }
   }
 
-  for (int64_t e = tid; e < (int64_t)R * n; e += T) tk.x_out[e] = x[e];
-  if (tk.z_out)
-    for (int64_t e = tid; e < (int64_t)R * m; e += T) tk.z_out[e] = z[e];
+  {
+    GLOBAL_AS double* xo = gptr(tk.x_out);
+    for (int64_t e = tid; e < (int64_t)R * n; e += T) xo[e] = x[e];
+  }
+  if (tk.z_out) {
+    GLOBAL_AS double* zo = gptr(tk.z_out);
+    for (int64_t e = tid; e < (int64_t)R * m; e += T) zo[e] = z[e];
+  }
   if (tid < R) tk.err2_out[tid] = checking ? etot[tid] : -1.0;
   if (tid == 0) {
     if (!stopping && status == 1) status = checking ? 1 : 0;
@@ -281,7 +586,6 @@ __global__ void __launch_bounds__(512) batch_solve_kernel(BatchArgs a) {
     case 1: run_task<TP, 1>(S, tk, a, lds, s_j, s_i); break;
     case 2: run_task<TP, 2>(S, tk, a, lds, s_j, s_i); break;
     case 4: run_task<TP, 4>(S, tk, a, lds, s_j, s_i); break;
-    case 8: run_task<TP, 8>(S, tk, a, lds, s_j, s_i); break;
     default: break;
   }
 }

@@ -90,13 +90,13 @@ __device__ __forceinline__ double wg_sum(double val, double* red) {
   return s;
 }
 
-// out[c] = sum_{r < rows} P[c * rows + r] * y[r] for c < w, P column-major (rows x w) in any
-// memory, y in LDS.  Each column gets T / w consecutive threads (coalesced along r); partial sums
+// out[c] = sum_{r < rows} P[c * ld + r] * y[r] for c < w, P column-major (rows x w, column stride
+// ld) in any memory, y in LDS.  Each column gets T / w consecutive threads (coalesced along r); partial sums
 // meet in red (blockDim slots).  Columns beyond blockDim.x are processed in chunks.  Ends with a
 // barrier.
 template <typename TP>
-__device__ __forceinline__ void colsum_colmajor(const TP* __restrict__ P, int64_t rows, int w, const double* y,
-                                                double* out, double* red) {
+__device__ __forceinline__ void colsum_colmajor(const TP* __restrict__ P, int64_t rows, int64_t ld, int w,
+                                                const double* y, double* out, double* red) {
   const int T = blockDim.x, tid = threadIdx.x;
   for (int cb = 0; cb < w; cb += T) {
     const int cw = min(T, w - cb);
@@ -104,7 +104,7 @@ __device__ __forceinline__ void colsum_colmajor(const TP* __restrict__ P, int64_
     const int c = cb + tid / gpc, g = tid % gpc;
     double acc = 0.0;
     if (tid / gpc < cw) {
-      const TP* col = P + (int64_t)c * rows;
+      const TP* col = P + (int64_t)c * ld;
       for (int64_t r = g; r < rows; r += gpc) acc += widen(col[r]) * y[r];
     }
     red[tid] = acc;

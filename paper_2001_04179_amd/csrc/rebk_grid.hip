@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     Src sr{nullptr, 0, nullptr, 0};
     if (qc >= 1 && nr > 0) {
       const int sl = slot(qc);
-      sr.c = Acol + m * s_c0[sl] + r0;
+      sr.c = Acol + a.ldc * s_c0[sl] + r0;
       sr.runs = s_nJ[sl];
     }
     if (qr >= 1 && nc > 0) {
@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   auto copy_plain = [&](const Src& sr, TP* dC, TP* dR) {  // every thread, ordinary loads
     for (int e = tid; e < sr.runs * nr; e += T) {
       const int c = e / nr, q = e - c * nr;
-      dC[e] = sr.c[(int64_t)c * m + q];
+      dC[e] = sr.c[(int64_t)c * a.ldc + q];
     }
     for (int e = tid; e < sr.lr; e += T) dR[e] = sr.r[e];
   };
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     TP* dR = slabR + (size_t)bufR * L.slabR;
     bool dma = false;
     if (tid >= 64) {  // waves 1..3: start the copies of the next slabs straight into LDS
-      dma = dma_runs(sr.c, m, sr.runs, nr, dC);
+      dma = dma_runs(sr.c, a.ldc, sr.runs, nr, dC);
       dma_runs(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
     }
     const unsigned long long* Gall = gs.gsum + (size_t)(epoch % kSumRing) * NG * E * 2;

@@ -18,7 +18,8 @@ struct DevStatus {
 // Everything a solve kernel needs; device pointers unless noted.
 struct SolveArgs {
   const void* Arow;          // row panels: block i is an n x nI_i column-major panel at n*row_off[i]
-  const void* Acol;          // column panels: A^T row-major; block j is an m x nJ_j column-major panel at m*col_off[j]
+  const void* Acol;          // column panels: A^T row-major with row stride ldc; block j is an m x nJ_j
+                             // column-major panel (column stride ldc) at ldc*col_off[j]
   const int64_t* row_off;    // s+1
   const int64_t* col_off;    // t+1
   const uint64_t* T_row;     // s cumulative 53-bit thresholds
@@ -26,6 +27,7 @@ struct SolveArgs {
   const double* coef_row;    // alpha / ||A_{I_i,:}||_F^2
   const double* coef_col;    // alpha / ||A_{:,J_j}||_F^2
   int64_t m, n;
+  int64_t ldc;               // column-panel stride: m rounded up to kColAlign entries (pad entries are 0)
   int32_t s, t;
   int32_t max_nI, max_nJ;
   uint64_t seed, sys;
@@ -57,7 +59,7 @@ struct GridSync {
 // One system of a batch: its panels, tables and Philox stream (device copy of the handle's data).
 struct BatchSys {
   const void* Arow;          // row panels, as in SolveArgs
-  const void* Acol;          // column panels (A^T row-major), as in SolveArgs
+  const void* Acol;          // column panels (A^T row-major, row stride ldc), as in SolveArgs
   const int64_t* row_off;
   const int64_t* col_off;
   const uint64_t* T_row;
@@ -65,6 +67,7 @@ struct BatchSys {
   const double* coef_row;
   const double* coef_col;
   int64_t m, n;
+  int64_t ldc;
   int32_t s, t;
   int32_t max_nI, max_nJ;
   uint64_t seed, sys;
@@ -74,7 +77,7 @@ struct BatchSys {
 // block sequence, so every panel element read serves all R of them).
 struct BatchTask {
   int32_t sys;               // index into the BatchSys array; -1: empty slot
-  int32_t R;                 // right-hand sides: 1, 2, 4 or 8
+  int32_t R;                 // right-hand sides: 1, 2 or 4
   const double* b;           // R vectors of length m, one after another
   const double* x_in;        // R vectors of length n, or NULL (x0 = 0)
   const double* x_ref;       // R vectors of length n, or NULL (no error check)
@@ -97,12 +100,17 @@ struct BatchArgs {
 };
 
 // Launchers (defined in rebk_kernels.hip).  All return hipError_t.
-hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype, int64_t m, int64_t n,
+// Column panels store every column of A in a run of ldc = roundup(m, kColAlign) entries, so every
+// run starts at a multiple of kColAlign entries (vector loads of 4 entries stay aligned).
+constexpr int64_t kColAlign = 16;
+inline int64_t col_stride(int64_t m) { return (m + kColAlign - 1) / kColAlign * kColAlign; }
+
+hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype, int64_t m, int64_t n, int64_t ldc,
                        const int64_t* row_off_d, const int64_t* col_off_d, const int32_t* rowblk_d,
                        const int32_t* colblk_d, void* Arow, void* Acol, hipStream_t st);
 hipError_t launch_finite_check(const void* A, int a_dtype, int64_t lda, int64_t m, int64_t n, int* bad,
                                hipStream_t st);
-hipError_t launch_block_weights(const void* Arow, const void* Acol, int panel_dtype, int64_t m, int64_t n,
+hipError_t launch_block_weights(const void* Arow, const void* Acol, int panel_dtype, int64_t m, int64_t n, int64_t ldc,
                                 const int64_t* row_off_d, int32_t s, const int64_t* col_off_d, int32_t t,
                                 const int32_t* rowblk_d, double* row_sq, double* colrow_sq, double* w_row,
                                 double* w_col, hipStream_t st);

@@ -43,10 +43,12 @@ __global__ void sample_kernel(const uint64_t* __restrict__ T_row, int s, const u
 
 // ------------------------------------------------------------------ packing
 
-// Column panels: A^T, row-major (n x m): entry (r, c) at c * m + r, so column block j is the
-// contiguous m x nJ_j column-major panel at offset m * col_off[j].  32 x 32 tiles through LDS.
+// Column panels: A^T, row-major (n x ldc, ldc >= m, pad entries zero): entry (r, c) at c * ldc + r,
+// so column block j is the contiguous m x nJ_j column-major panel (column stride ldc) at offset
+// ldc * col_off[j].  32 x 32 tiles through LDS.
 template <typename TIn, typename TP>
-__global__ void pack_col_kernel(const TIn* __restrict__ A, int64_t lda, int64_t m, int64_t n, TP* __restrict__ Acol) {
+__global__ void pack_col_kernel(const TIn* __restrict__ A, int64_t lda, int64_t m, int64_t n, int64_t ldc,
+                                TP* __restrict__ Acol) {
   __shared__ double tile[32][33];
   for (int64_t R = (int64_t)blockIdx.y * 32; R < m; R += (int64_t)gridDim.y * 32) {
     for (int64_t C = (int64_t)blockIdx.x * 32; C < n; C += (int64_t)gridDim.x * 32) {
@@ -57,7 +59,7 @@ __global__ void pack_col_kernel(const TIn* __restrict__ A, int64_t lda, int64_t 
       __syncthreads();
       for (int q = threadIdx.y; q < 32; q += blockDim.y) {
         const int64_t r = R + threadIdx.x, c = C + q;
-        if (r < m && c < n) Acol[c * m + r] = narrow<TP>(tile[threadIdx.x][q]);
+        if (r < m && c < n) Acol[c * ldc + r] = narrow<TP>(tile[threadIdx.x][q]);
       }
       __syncthreads();
     }
@@ -123,17 +125,17 @@ __global__ void row_sq_kernel(const TP* __restrict__ Arow, int64_t m, int64_t n,
 }
 
 template <typename TP>
-__global__ void colrow_sq_kernel(const TP* __restrict__ Acol, int64_t m, const int64_t* __restrict__ col_off, int t,
-                                 double* __restrict__ colrow_sq) {
+__global__ void colrow_sq_kernel(const TP* __restrict__ Acol, int64_t m, int64_t ldc, const int64_t* __restrict__ col_off,
+                                 int t, double* __restrict__ colrow_sq) {
 #pragma clang fp contract(off)
   const int64_t total = m * (int64_t)t;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = e / m, r = e - j * m;
     const int64_t c0 = col_off[j], nJ = col_off[j + 1] - c0;
-    const TP* p = Acol + m * c0 + r;
+    const TP* p = Acol + ldc * c0 + r;
     double acc = 0.0;
     for (int64_t c = 0; c < nJ; ++c) {
-      const double v = widen(p[c * m]);
+      const double v = widen(p[c * ldc]);
       const double sq = v * v;
       acc = acc + sq;
     }
@@ -216,12 +218,12 @@ __global__ void __launch_bounds__(kWgThreads) wg_solve_kernel(SolveArgs a) {
     // z^k = z^{k-1} - alpha/||A_{:,J}||_F^2 * A_{:,J} (A_{:,J}^T z^{k-1})
     const int64_t c0 = a.col_off[j];
     const int nJ = (int)(a.col_off[j + 1] - c0);
-    const TP* __restrict__ P = Acol + m * c0;  // (r, c) at c * m + r
-    colsum_colmajor(P, m, nJ, z, v, red);
+    const TP* __restrict__ P = Acol + a.ldc * c0;  // (r, c) at c * ldc + r
+    colsum_colmajor(P, m, a.ldc, nJ, z, v, red);
     const double cc = a.coef_col[j];
     for (int64_t r = tid; r < m; r += T) {
       double acc = 0.0;
-      for (int c = 0; c < nJ; ++c) acc += widen(P[c * m + r]) * v[c];
+      for (int c = 0; c < nJ; ++c) acc += widen(P[c * a.ldc + r]) * v[c];
       z[r] -= cc * acc;
     }
     __syncthreads();
@@ -309,9 +311,9 @@ __global__ void residual_kernel(SolveArgs a, const double* __restrict__ x, const
     const double f = a.b[l] - z[l] - acc;
     f2 += f * f;
   }
-  // columns of A^T z through the column panels (A^T, row-major): entry (r, c) at c * m + r
+  // columns of A^T z through the column panels (A^T, row-major): entry (r, c) at c * ldc + r
   for (int64_t c = (int64_t)blk * blockDim.x + tid; c < n; c += (int64_t)nb * blockDim.x) {
-    const TP* p = Acol + c * m;
+    const TP* p = Acol + c * a.ldc;
     double acc = 0.0;
     for (int64_t r = 0; r < m; ++r) acc += widen(p[r]) * z[r];
     g2 += acc * acc;
@@ -340,7 +342,7 @@ __global__ void err2_kernel(const double* __restrict__ x, const double* __restri
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype, int64_t m, int64_t n,
+hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype, int64_t m, int64_t n, int64_t ldc,
                        const int64_t* row_off_d, const int64_t* col_off_d, const int32_t* rowblk_d,
                        const int32_t* colblk_d, void* Arow, void* Acol, hipStream_t st) {
   return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
@@ -351,12 +353,12 @@ hipError_t launch_pack(const void* A, int a_dtype, int64_t lda, int panel_dtype,
     const unsigned tx = (unsigned)((n + 31) / 32 < 65535 ? (n + 31) / 32 : 65535);
     if (a_dtype == 0) {
       hipLaunchKernelGGL((pack_col_kernel<double, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const double*)A, lda, m, n,
-                         (TP*)Acol);
+                         ldc, (TP*)Acol);
       hipLaunchKernelGGL((pack_row_kernel<double, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const double*)A, lda, m, n,
                          row_off_d, rowblk_d, (TP*)Arow);
     } else {
       hipLaunchKernelGGL((pack_col_kernel<float, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const float*)A, lda, m, n,
-                         (TP*)Acol);
+                         ldc, (TP*)Acol);
       hipLaunchKernelGGL((pack_row_kernel<float, TP>), dim3(tx, ty), dim3(32, 8), 0, st, (const float*)A, lda, m, n,
                          row_off_d, rowblk_d, (TP*)Arow);
     }
@@ -375,7 +377,7 @@ hipError_t launch_finite_check(const void* A, int a_dtype, int64_t lda, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_block_weights(const void* Arow, const void* Acol, int panel_dtype, int64_t m, int64_t n,
+hipError_t launch_block_weights(const void* Arow, const void* Acol, int panel_dtype, int64_t m, int64_t n, int64_t ldc,
                                 const int64_t* row_off_d, int32_t s, const int64_t* col_off_d, int32_t t,
                                 const int32_t* rowblk_d, double* row_sq, double* colrow_sq, double* w_row,
                                 double* w_col, hipStream_t st) {
@@ -386,7 +388,7 @@ hipError_t launch_block_weights(const void* Arow, const void* Acol, int panel_dt
                        row_sq);
     const int64_t tot = m * (int64_t)t;
     const unsigned g2 = (unsigned)((tot + 255) / 256 < 8192 ? (tot + 255) / 256 : 8192);
-    hipLaunchKernelGGL((colrow_sq_kernel<TP>), dim3(g2), dim3(256), 0, st, (const TP*)Acol, m, col_off_d, t, colrow_sq);
+    hipLaunchKernelGGL((colrow_sq_kernel<TP>), dim3(g2), dim3(256), 0, st, (const TP*)Acol, m, ldc, col_off_d, t, colrow_sq);
     hipLaunchKernelGGL(sum_rows_kernel, dim3((s + 63) / 64), dim3(64), 0, st, row_sq, row_off_d, s, w_row);
     hipLaunchKernelGGL(sum_cols_kernel, dim3((t + 63) / 64), dim3(64), 0, st, colrow_sq, m, t, w_col);
     return hipGetLastError();

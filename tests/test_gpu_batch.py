@@ -49,7 +49,7 @@ def oracle_check(oracle, systems, out, iters_per_rhs, stored=None, rtol=RTOL_F64
             q += 1
 
 
-@pytest.mark.parametrize("threads,max_tile", [(256, 1), (512, 2), (256, 4), (512, 8)])
+@pytest.mark.parametrize("threads,max_tile", [(256, 1), (512, 2), (256, 4), (512, 4)])
 def test_batch_fixed_iterations_match_oracle(rebk, oracle_lib, threads, max_tile):
     systems = small_batch()
     solvers, batch = make_batch(rebk, systems)
@@ -134,7 +134,7 @@ def test_batch_autotune_then_solve(rebk, oracle_lib):
     solvers, batch = make_batch(rebk, systems)
     B = [to_dev(S.B) for S in systems]
     cfg = batch.autotune(B, probe_iters=16)
-    assert cfg["threads"] in (256, 512) and cfg["max_tile"] in (1, 2, 4, 8) and cfg["xcd_order"] in (0, 1)
+    assert cfg["threads"] in (256, 512) and cfg["max_tile"] in (1, 2, 4) and cfg["xcd_order"] in (0, 1)
     assert cfg["ms"] > 0
     out = batch.solve(B, max_iter=60)
     oracle_check(oracle_lib, systems, out, out["iterations"])
@@ -152,7 +152,7 @@ def test_batch_invalid_arguments(rebk):
     with pytest.raises(rebk.RebkError):
         batch.solve(B, max_iter=10, threads=384)
     with pytest.raises(rebk.RebkError):
-        batch.solve(B, max_iter=10, max_tile=3)
+        batch.solve(B, max_iter=10, max_tile=8)
     with pytest.raises(rebk.RebkError):
         batch.solve(B, max_iter=10, lds_budget=256)    # no system fits
     other = rebk.Solver(to_dev(systems[0].A), systems[0].row_off, systems[0].col_off, systems[0].alpha, 0,
