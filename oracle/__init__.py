@@ -59,6 +59,9 @@ def _load():
     lib.oracle_rebk_solve.argtypes = [P, I64, I64, I64, P, I64, P, I64, ctypes.c_double, U64, U64,
                                       P, P, P, I64, I64, P, ctypes.c_double, P, P, P, P, P, P]
     lib.oracle_rebk_solve.restype = ctypes.c_int
+    lib.oracle_rebk_refine.argtypes = [P, P, I64, I64, I64, P, I64, P, I64, ctypes.c_double, U64, U64,
+                                       P, P, P, ctypes.c_double, I64, I64, P, P, P, P, P, P]
+    lib.oracle_rebk_refine.restype = ctypes.c_int
     lib.oracle_philox_fill.argtypes = [P, P, I64, P]
     lib.oracle_philox_fill.restype = None
     lib.oracle_sample_blocks.argtypes = [P, I64, P, I64, U64, U64, I64, I64, P, P]
@@ -178,3 +181,39 @@ def rebk_solve(A, row_off, col_off, alpha, seed, b, *, x0=None, z0=None, k0=0, m
         out["j"] = jt[:k].copy()
         out["i"] = it[:k].copy()
     return out
+
+
+def rebk_refine(A, A_stored, row_off, col_off, alpha, seed, b, *, x0=None, x_ref=None, tol=0.0, inner_iters=100,
+                max_outer=10, sys=0):
+    """FP64 iterative refinement of the augmented least-squares system with Algorithm 1 as the
+    inner solver on A_stored (the stored panel values), residuals and x-updates on A.
+
+    Returns dict(x, z, err_trace (one entry per tested outer step), outer, iterations, err, status
+    (0 stopped on tol, 1 max_outer reached))."""
+    lib = _load()
+    A = _f64(A)
+    Ast = _f64(A_stored)
+    m, n = A.shape
+    if Ast.shape != A.shape:
+        raise ValueError("A_stored must have A's shape")
+    ro, co = _i64(row_off), _i64(col_off)
+    s, t = len(ro) - 1, len(co) - 1
+    b = _f64(b)
+    x0 = _f64(x0)
+    x_ref = _f64(x_ref)
+    x = np.zeros(n)
+    z = np.zeros(m)
+    trace = np.full(int(max_outer) + 1, np.nan)
+    outer = np.zeros(1, dtype=np.int64)
+    iters = np.zeros(1, dtype=np.int64)
+    err = np.zeros(1)
+    st = lib.oracle_rebk_refine(_ptr(A), _ptr(Ast), m, n, n, _ptr(ro), s, _ptr(co), t, float(alpha),
+                                ctypes.c_uint64(int(seed)), ctypes.c_uint64(int(sys)), _ptr(b), _ptr(x0),
+                                _ptr(x_ref), float(tol), int(inner_iters), int(max_outer), _ptr(x), _ptr(z),
+                                _ptr(trace), _ptr(outer), _ptr(iters), _ptr(err))
+    if st < 0:
+        raise ValueError("invalid refinement input")
+    tested = int(outer[0]) + 1
+    return {"x": x, "z": z, "err_trace": trace[:tested], "outer": int(outer[0]), "iterations": int(iters[0]),
+            "err": float(err[0]), "status": int(st)}
+

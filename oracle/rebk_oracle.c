@@ -179,16 +179,23 @@ static double orc_rel_err(const double *x, const double *xr, int64_t n)
  * Returns 0 (stopped on tol or no x_ref given), 1 (max_iter reached with
  * x_ref given and tol not met), -1 (invalid input).
  */
-int oracle_rebk_solve(const double *A, int64_t m, int64_t n, int64_t lda,
-                      const int64_t *row_off, int64_t s,
-                      const int64_t *col_off, int64_t t,
-                      double alpha, uint64_t seed, uint64_t sys,
-                      const double *b, const double *x0, const double *z0,
-                      int64_t k0, int64_t max_iter,
-                      const double *x_ref, double tol,
-                      double *x, double *z,
-                      int32_t *j_trace, int32_t *i_trace,
-                      int64_t *iters, double *err)
+/*
+ * Algorithm 1's iteration with two optional extensions used by the refinement below:
+ *   g (n entries): the z-step uses v = A_J^T z - g_J, i.e. it projects onto {A^T z = g};
+ *   y (m entries): set to 0, then y_I -= coef_I u after every x-step, so that x - x0 = A^T y.
+ * With g = y = NULL this is exactly Algorithm 1.
+ */
+static int orc_iterate(const double *A, int64_t m, int64_t n, int64_t lda,
+                       const int64_t *row_off, int64_t s,
+                       const int64_t *col_off, int64_t t,
+                       double alpha, uint64_t seed, uint64_t sys,
+                       const double *b, const double *x0, const double *z0,
+                       int64_t k0, int64_t max_iter,
+                       const double *x_ref, double tol,
+                       const double *g, double *y,
+                       double *x, double *z,
+                       int32_t *j_trace, int32_t *i_trace,
+                       int64_t *iters, double *err)
 {
     if (m <= 0 || n <= 0 || s <= 0 || t <= 0 || lda < n || !(alpha > 0.0)) return -1;
     double *w_row = (double *)malloc(sizeof(double) * (size_t)s);
@@ -213,6 +220,8 @@ int oracle_rebk_solve(const double *A, int64_t m, int64_t n, int64_t lda,
     /* initial iterates (Algorithm 1; Section 3 uses z0 = b, x0 = 0) */
     for (int64_t c = 0; c < n; ++c) x[c] = x0 ? x0[c] : 0.0;
     for (int64_t r = 0; r < m; ++r) z[r] = z0 ? z0[r] : b[r];
+    if (y)
+        for (int64_t r = 0; r < m; ++r) y[r] = 0.0;
 
     *iters = 0;
     *err = -1.0;
@@ -232,7 +241,7 @@ int oracle_rebk_solve(const double *A, int64_t m, int64_t n, int64_t lda,
         for (int64_t c = c_lo; c < c_hi; ++c) {
             double acc = 0.0;
             for (int64_t r = 0; r < m; ++r) acc = acc + A[r * lda + c] * z[r];
-            v[c - c_lo] = acc;
+            v[c - c_lo] = g ? acc - g[c] : acc;
         }
         for (int64_t r = 0; r < m; ++r) {
             double acc = 0.0;
@@ -255,6 +264,8 @@ int oracle_rebk_solve(const double *A, int64_t m, int64_t n, int64_t lda,
             for (int64_t r = r_lo; r < r_hi; ++r) acc = acc + A[r * lda + c] * u[r - r_lo];
             x[c] = x[c] - coef_r * acc;
         }
+        if (y)
+            for (int64_t r = r_lo; r < r_hi; ++r) y[r] = y[r] - coef_r * u[r - r_lo];
 
         if (j_trace) j_trace[step] = (int32_t)j;
         if (i_trace) i_trace[step] = (int32_t)i;
@@ -270,6 +281,120 @@ int oracle_rebk_solve(const double *A, int64_t m, int64_t n, int64_t lda,
 
 done:
     free(w_row); free(w_col); free(T_row); free(T_col); free(u); free(v);
+    return status;
+}
+
+int oracle_rebk_solve(const double *A, int64_t m, int64_t n, int64_t lda,
+                      const int64_t *row_off, int64_t s,
+                      const int64_t *col_off, int64_t t,
+                      double alpha, uint64_t seed, uint64_t sys,
+                      const double *b, const double *x0, const double *z0,
+                      int64_t k0, int64_t max_iter,
+                      const double *x_ref, double tol,
+                      double *x, double *z,
+                      int32_t *j_trace, int32_t *i_trace,
+                      int64_t *iters, double *err)
+{
+    return orc_iterate(A, m, n, lda, row_off, s, col_off, t, alpha, seed, sys, b, x0, z0, k0, max_iter,
+                       x_ref, tol, NULL, NULL, x, z, j_trace, i_trace, iters, err);
+}
+
+/*
+ * Iterative refinement of the augmented system of least squares, REBK as the inner solver.
+ * (Not in the paper: an FP64 outer loop around Algorithm 1, so that the inner iterations may
+ * run on rounded panel values.)
+ *
+ * The solution pair of  z + A x = b,  A^T z = 0,  x in range(A^T)  is z = (I - A A^+) b (the limit
+ * of Lemma 6) and x = A^+ b (the limit of Theorem 7).  For a current pair (z, x) the residuals
+ *   f = b - z - A x,   g = -A^T z
+ * define the correction (dz, dx):  dz + A dx = f,  A^T dz = g.  Algorithm 1 solves it when its
+ * z-step projects onto {A^T dz = g} (v = A_J^T dz - g_J) and its x-step solves A dx = f - dz,
+ * started from dz = f, dx = 0 (z0 in f + range(A), x0 in range(A^T) as Theorem 7 asks).
+ * The inner iterations run on Ast (the stored, possibly rounded, values; the block weights and
+ * sampling tables are Ast's), the residuals and the update of x on the FP64 A:
+ *   z += dz,   x += A^T dy   (dy: the x-steps' coefficients, dx = Ast^T dy),
+ * so x stays in range(A^T) whatever the rounding of Ast.  The inner block sequence continues
+ * the Philox counter across outer steps (outer step q runs iterations q*inner_iters + 1 ...).
+ *
+ * Stop rule, tested before every outer step and after the last one: with x_ref,
+ * ||x - x_ref|| / ||x_ref|| < tol; without, ||f|| <= tol ||b|| and ||g|| <= tol ||A||_F ||b||.
+ * err_trace (max_outer + 1 entries, may be NULL) receives the tested quantity (with x_ref the
+ * relative error, else max(||f|| / ||b||, ||g|| / (||A||_F ||b||))) before each outer step.
+ * Returns 0 (stopped on tol), 1 (max_outer reached), -1 (invalid input).
+ */
+int oracle_rebk_refine(const double *A, const double *Ast, int64_t m, int64_t n, int64_t lda,
+                       const int64_t *row_off, int64_t s,
+                       const int64_t *col_off, int64_t t,
+                       double alpha, uint64_t seed, uint64_t sys,
+                       const double *b, const double *x0, const double *x_ref, double tol,
+                       int64_t inner_iters, int64_t max_outer,
+                       double *x, double *z, double *err_trace,
+                       int64_t *outer_done, int64_t *iters, double *err)
+{
+    if (m <= 0 || n <= 0 || lda < n || inner_iters <= 0 || max_outer < 0) return -1;
+    double *f = (double *)malloc(sizeof(double) * (size_t)m);
+    double *g = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dz = (double *)malloc(sizeof(double) * (size_t)m);
+    double *dx = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dy = (double *)malloc(sizeof(double) * (size_t)m);
+    int status = 1;
+    double bn = 0.0, an = 0.0;
+    for (int64_t r = 0; r < m; ++r) bn = bn + b[r] * b[r];
+    for (int64_t r = 0; r < m; ++r)
+        for (int64_t c = 0; c < n; ++c) an = an + A[r * lda + c] * A[r * lda + c];
+    bn = sqrt(bn);
+    an = sqrt(an);
+    for (int64_t c = 0; c < n; ++c) x[c] = x0 ? x0[c] : 0.0;
+    for (int64_t r = 0; r < m; ++r) z[r] = b[r];
+    *iters = 0;
+    *outer_done = 0;
+    for (int64_t q = 0;; ++q) {
+        /* f = b - z - A x, g = -A^T z (FP64, plain loops) */
+        double f2 = 0.0, g2 = 0.0;
+        for (int64_t r = 0; r < m; ++r) {
+            double acc = 0.0;
+            for (int64_t c = 0; c < n; ++c) acc = acc + A[r * lda + c] * x[c];
+            f[r] = (b[r] - z[r]) - acc;
+            f2 = f2 + f[r] * f[r];
+        }
+        for (int64_t c = 0; c < n; ++c) {
+            double acc = 0.0;
+            for (int64_t r = 0; r < m; ++r) acc = acc + A[r * lda + c] * z[r];
+            g[c] = -acc;
+            g2 = g2 + g[c] * g[c];
+        }
+        double e;
+        int ok;
+        if (x_ref) {
+            e = orc_rel_err(x, x_ref, n);
+            ok = e < tol;
+        } else {
+            double rf = sqrt(f2) / (bn > 0.0 ? bn : 1.0);
+            double rg = sqrt(g2) / (an * bn > 0.0 ? an * bn : 1.0);
+            e = rf > rg ? rf : rg;
+            ok = rf <= tol && rg <= tol;
+        }
+        if (err_trace) err_trace[q] = e;
+        *err = e;
+        if (ok) { status = 0; break; }
+        if (q == max_outer) break;
+        /* correction: Algorithm 1 on (f, g) from dz = f, dx = 0 */
+        int64_t it = 0;
+        double ie = -1.0;
+        int st = orc_iterate(Ast, m, n, lda, row_off, s, col_off, t, alpha, seed, sys, f, NULL, f,
+                             q * inner_iters, inner_iters, NULL, 0.0, g, dy, dx, dz, NULL, NULL, &it, &ie);
+        if (st < 0) { status = -1; break; }
+        *iters += it;
+        /* z += dz, x += A^T dy */
+        for (int64_t r = 0; r < m; ++r) z[r] = z[r] + dz[r];
+        for (int64_t c = 0; c < n; ++c) {
+            double acc = 0.0;
+            for (int64_t r = 0; r < m; ++r) acc = acc + A[r * lda + c] * dy[r];
+            x[c] = x[c] + acc;
+        }
+        *outer_done = q + 1;
+    }
+    free(f); free(g); free(dz); free(dx); free(dy);
     return status;
 }
 

@@ -211,10 +211,16 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   }
   if (kernel != REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel %d", kernel);
   int G = grid_wgs > 0 ? grid_wgs : h->cus;
-  const size_t lds = rebk::grid_solve_lds_bytes(a, G, h->panel_dtype);
+  // row slabs staged in LDS when they fit, else read from the row panels in HBM
+  bool row_lds = true;
+  size_t lds = rebk::grid_solve_lds_bytes(a, G, h->panel_dtype, true);
+  if (lds > 160 * 1024) {
+    row_lds = false;
+    lds = rebk::grid_solve_lds_bytes(a, G, h->panel_dtype, false);
+  }
   if (lds > 160 * 1024) return fail(REBK_ERR_INVALID, "grid kernel needs %zu bytes of LDS per workgroup", lds);
   int per_cu = 0;
-  HIP_TRY(rebk::grid_solve_max_blocks(h->panel_dtype, lds, &per_cu));
+  HIP_TRY(rebk::grid_solve_max_blocks(h->panel_dtype, lds, row_lds, &per_cu));
   if (per_cu <= 0 || G > per_cu * h->cus)
     return fail(REBK_ERR_INVALID, "grid of %d workgroups cannot be co-resident (%d per CU)", G, per_cu);
   if ((h->n + G - 1) / G > rebk::kGridThreads)
@@ -236,7 +242,7 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   HIP_TRY(hipMemsetAsync(h->part, 0, part_words * sizeof(unsigned long long), h->stream));
   HIP_TRY(hipMemsetAsync(h->gsum, 0, gsum_words * sizeof(unsigned long long), h->stream));
   HIP_TRY(hipMemsetAsync(h->timeout, 0, sizeof(int), h->stream));
-  HIP_TRY(rebk::launch_grid_solve(a, gs, h->panel_dtype, G, h->stream));
+  HIP_TRY(rebk::launch_grid_solve(a, gs, h->panel_dtype, G, row_lds, h->stream));
   return REBK_OK;
 }
 

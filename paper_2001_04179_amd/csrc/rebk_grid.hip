@@ -86,13 +86,16 @@ struct GridLayout {
   size_t slabR;   // panel elements of one row-slab buffer
 };
 
-__host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int max_nI, int max_nJ, int G, int threads) {
+// row_lds: the row slabs are staged in LDS (else the x-steps read them from the row panels in HBM,
+// for systems whose slabs do not fit).
+__host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int max_nI, int max_nJ, int G, int threads,
+                                                  bool row_lds = true) {
   GridLayout L;
   L.NR = (int)((m + G - 1) / G);
   L.NC = (int)((n + G - 1) / G);
-  L.dbl = 3 * (size_t)L.NR + 2 * (size_t)L.NC + (size_t)max_nJ + (size_t)max_nI + (size_t)threads + 8;
+  L.dbl = 4 * (size_t)L.NR + 2 * (size_t)L.NC + (size_t)max_nJ + (size_t)max_nI + (size_t)threads + 8;
   L.slabC = (size_t)L.NR * max_nJ;
-  L.slabR = (size_t)L.NC * max_nI;
+  L.slabR = row_lds ? (size_t)L.NC * max_nI : 0;
   return L;
 }
 
@@ -146,7 +149,7 @@ __device__ __forceinline__ bool dma_runs(const TP* src, int64_t stride, int runs
   return true;
 }
 
-template <typename TP>
+template <typename TP, bool RowLds>
 __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, GridSync gs) {
   extern __shared__ double lds[];
   // per-draw metadata: blocks, their sizes, panel offsets and step coefficients
@@ -158,7 +161,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
   const int64_t m = a.m, n = a.n;
   const int MJ = a.max_nJ, MI = a.max_nI;
-  const GridLayout L = grid_layout(m, n, MI, MJ, G, T);
+  const GridLayout L = grid_layout(m, n, MI, MJ, G, T, RowLds);
   const int64_t r0 = (int64_t)w * m / G, r1 = (int64_t)(w + 1) * m / G;
   const int64_t cA = (int64_t)w * n / G, cB = (int64_t)(w + 1) * n / G;
   const int nr = (int)(r1 - r0), nc = (int)(cB - cA);
@@ -170,6 +173,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   double* xr = x + L.NC;    // x_ref on owned columns
   double* v = xr + L.NC;    // reduced A_{:,J}^T z
   double* u = v + MJ;       // reduced A_{I,:} x - b_I + z_I
+  double* yv = u + MI + T + 8;  // y on owned rows (refinement), after the reduction scratch
   TP* slabC = (TP*)(lds + L.dbl);
   TP* slabR = slabC + 2 * L.slabC;
 
@@ -194,6 +198,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     x[q] = a.x_in ? a.x_in[cA + q] : 0.0;
     xr[q] = a.x_ref ? a.x_ref[cA + q] : 0.0;
   }
+  for (int q = tid; q < nr; q += T) yv[q] = 0.0;
 
   auto refill = [&](int64_t first) {  // draws of relative iterations first .. first+63
     if (tid < 64) {
@@ -235,12 +240,40 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       sr.c = Acol + a.ldc * s_c0[sl] + r0;
       sr.runs = s_nJ[sl];
     }
-    if (qr >= 1 && nc > 0) {
+    if (RowLds && qr >= 1 && nc > 0) {
       const int sl = slot(qr);
       sr.r = Arow + n * s_r0[sl] + cA * s_nI[sl];
       sr.lr = nc * s_nI[sl];
     }
     return sr;
+  };
+  // row slab of iteration q (owned columns of row block I_q, column-major nc x |I_q|): in LDS
+  // buffer `buf`, or straight from the row panel
+  auto row_src = [&](int64_t q, int buf) -> const TP* {
+    if constexpr (RowLds) {
+      (void)q;
+      return slabR + (size_t)buf * L.slabR;
+    } else {
+      (void)buf;
+      const int sl = slot(q);
+      return Arow + n * s_r0[sl] + cA * s_nI[sl];
+    }
+  };
+  // refinement: v^{q} -= g_J (the z-step then projects onto {A^T z = g}); all threads call it
+  auto apply_g = [&](int64_t q) {
+    if (a.g == nullptr || q < 1 || q > K) return;
+    const int sl = slot(q);
+    const int64_t c0 = s_c0[sl];
+    for (int c = tid; c < s_nJ[sl]; c += T) v[c] -= a.g[c0 + c];
+    __syncthreads();
+  };
+  // refinement: y_I -= coef_I u^q on the owned rows of I_q (the x-step is x -= A_I^T (coef_I u))
+  auto yupdate = [&](int64_t q) {
+    const int sl = slot(q);
+    const int64_t rI = s_r0[sl], rE = rI + s_nI[sl];
+    const int64_t lo = rI > r0 ? rI : r0, hi = rE < r1 ? rE : r1;
+    const double cr = s_cr[sl];
+    for (int64_t l = lo + tid; l < hi; l += T) yv[l - r0] -= cr * u[l - rI];
   };
   auto copy_plain = [&](const Src& sr, TP* dC, TP* dR) {  // every thread, ordinary loads
     for (int e = tid; e < sr.runs * nr; e += T) {
@@ -311,7 +344,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     }
     const Src sr = slab_src(qc, qr);
     TP* dC = slabC + (size_t)bufC * L.slabC;
-    TP* dR = slabR + (size_t)bufR * L.slabR;
+    TP* dR = RowLds ? slabR + (size_t)bufR * L.slabR : slabR;
     bool dma = false;
     if (tid >= 64) {  // waves 1..3: start the copies of the next slabs straight into LDS
       dma = dma_runs(sr.c, a.ldc, sr.runs, nr, dC);
@@ -459,6 +492,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     const int nJ1 = s_nJ[slot(1)];
     push_q(d1, nJ1, gs.part + (size_t)w * E * 2, epoch + 1);
     alive = sync_round(++epoch, 0, nJ1, 0, false, K >= 2 ? 2 : 0, 0, 1, 1);
+    if (alive) apply_g(1);
   }
 
   int64_t rr = 1;
@@ -480,7 +514,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 
     // phase A: z^k on owned rows (column slab of J_k); x^{k-1} on owned columns (row slab of I_{k-1})
     zupdate(slabC + (size_t)(rr & 1) * L.slabC, nJk, s_cc[sk]);
-    if (nIp > 0 && nc > 0) xupdate(slabR + (size_t)((rr - 1) & 1) * L.slabR, nIp, s_cr[slot(rr - 1)]);
+    if (nIp > 0 && nc > 0) xupdate(row_src(rr - 1, (int)((rr - 1) & 1)), nIp, s_cr[slot(rr - 1)]);
+    if (nIp > 0 && a.y_out) yupdate(rr - 1);
     __syncthreads();
     // phase B: this workgroup's partial vector: A_{:,J_{k+1}}^T z^k (row groups), A_{I_k,C} x^{k-1}
     // + (z^k - b) on owned rows of I_k, and ||x^{k-1} - x_ref||^2
@@ -489,7 +524,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     const bool has_err = checking && rr >= 2 && ((rr - 1) % ce == 0);
     if (nJn > 0) push_q(slabC + (size_t)((rr + 1) & 1) * L.slabC, nJn, P, ep);
     {
-      const TP* Sr = slabR + (size_t)(rr & 1) * L.slabR;
+      const TP* Sr = row_src(rr, (int)(rr & 1));
       const int64_t rI = s_r0[sk];
       for (int l = tid; l < nIk; l += T) {
         double acc = 0.0;
@@ -504,6 +539,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     alive = sync_round(++epoch, (int)(rr & 1), nJn, nIk, has_err, rr + 2 <= K ? rr + 2 : 0, (int)(rr & 1),
                        rr + 1 <= K ? rr + 1 : 0, (int)((rr + 1) & 1));
     if (!alive) break;
+    if (nJn > 0) apply_g(rr + 1);
     // v = v^{k+1}, u = u^k, s_err2 = ||x^{k-1} - x_ref||^2
     if (has_err) {
       const double e2 = s_err2;
@@ -524,7 +560,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   if (alive && !stopped) {
     // epilogue: x^K from u^K, then the error of x^K
     const int sK = slot(K);
-    if (nc > 0) xupdate(slabR + (size_t)(K & 1) * L.slabR, s_nI[sK], s_cr[sK]);
+    if (nc > 0) xupdate(row_src(K, (int)(K & 1)), s_nI[sK], s_cr[sK]);
+    if (a.y_out) yupdate(K);
     __syncthreads();
     last_k = a.k0 + K;
     if (a.x_ref != nullptr) {
@@ -553,6 +590,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   for (int q = tid; q < nr; q += T)
     if (a.z_out) a.z_out[r0 + q] = z[q];
   for (int q = tid; q < nc; q += T) a.x_out[cA + q] = x[q];
+  if (a.y_out)
+    for (int q = tid; q < nr; q += T) a.y_out[r0 + q] = yv[q];
   if (w == 0 && tid == 0) {
     a.status->status = alive ? status : -4;
     a.status->stopped = stopped;
@@ -564,35 +603,39 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 
 }  // namespace
 
-size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype) {
-  const GridLayout L = grid_layout(a.m, a.n, a.max_nI, a.max_nJ, grid, kGridThreads);
+size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype, bool row_lds) {
+  const GridLayout L = grid_layout(a.m, a.n, a.max_nI, a.max_nJ, grid, kGridThreads, row_lds);
   const size_t esz = panel_dtype == 0 ? 8 : (panel_dtype == 1 ? 4 : 2);
   return L.dbl * sizeof(double) + 2 * (L.slabC + L.slabR) * esz + 64;
 }
 
-hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu) {
+template <typename TP>
+const void* grid_kernel_ptr(bool row_lds) {
+  return row_lds ? (const void*)grid_solve_kernel<TP, true> : (const void*)grid_solve_kernel<TP, false>;
+}
+
+hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, bool row_lds, int* blocks_per_cu) {
   return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
     using TP = typename decltype(tag)::T;
-    hipError_t e = hipFuncSetAttribute((const void*)grid_solve_kernel<TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_bytes);
+    const void* k = grid_kernel_ptr<TP>(row_lds);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)grid_solve_kernel<TP>, kGridThreads,
-                                                        lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kGridThreads, lds_bytes);
   });
 }
 
-hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_dtype, int grid, hipStream_t st) {
+hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_dtype, int grid, bool row_lds,
+                             hipStream_t st) {
   return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
     using TP = typename decltype(tag)::T;
-    const size_t lds = grid_solve_lds_bytes(a, grid, panel_dtype);
-    hipError_t e = hipFuncSetAttribute((const void*)grid_solve_kernel<TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    const void* k = grid_kernel_ptr<TP>(row_lds);
+    const size_t lds = grid_solve_lds_bytes(a, grid, panel_dtype, row_lds);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     SolveArgs aa = a;
     GridSync gg = gs;
     void* args[] = {&aa, &gg};
-    return hipLaunchCooperativeKernel((const void*)grid_solve_kernel<TP>, dim3(grid), dim3(kGridThreads), args,
-                                      (unsigned)lds, st);
+    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kGridThreads), args, (unsigned)lds, st);
   });
 }
 

@@ -37,6 +37,10 @@ struct SolveArgs {
   double* x_out;
   double* z_out;             // may be NULL
   const double* x_ref;       // NULL: no reference error
+  const double* g;           // NULL, or n entries: the z-step projects onto {A^T z = g} instead of
+                             // {A^T z = 0} (correction equations of the refinement)
+  double* y_out;             // NULL, or m entries: receives y with x - x_in = A^T y accumulated over
+                             // this call's x-steps (y_I -= coef_I u), starting from 0
   double xref_sq;            // ||x_ref||^2 (host-computed)
   double tol;                // relative tolerance (<= 0: none)
   int64_t k0;
@@ -121,9 +125,11 @@ hipError_t launch_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uin
                          int64_t count, uint64_t* out, hipStream_t st);
 hipError_t launch_wg_solve(const SolveArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st);
 size_t wg_solve_lds_bytes(const SolveArgs& a);
-hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_dtype, int grid, hipStream_t st);
-size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype);
-hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu);
+// row_lds: stage the row slabs in LDS (else the x-steps read them from HBM)
+hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_dtype, int grid, bool row_lds,
+                             hipStream_t st);
+size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype, bool row_lds);
+hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, bool row_lds, int* blocks_per_cu);
 hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, const SolveArgs& a,
                            const double* x, const double* z, double* partials, int nparts, hipStream_t st);
 size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads);

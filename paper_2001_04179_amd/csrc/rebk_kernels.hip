@@ -189,6 +189,8 @@ __global__ void __launch_bounds__(kWgThreads) wg_solve_kernel(SolveArgs a) {
 
   for (int64_t r = tid; r < m; r += T) z[r] = a.z_in ? a.z_in[r] : a.b[r];
   for (int64_t c = tid; c < n; c += T) x[c] = a.x_in ? a.x_in[c] : 0.0;
+  if (a.y_out)
+    for (int64_t r = tid; r < m; r += T) a.y_out[r] = 0.0;
   __syncthreads();
 
   const int64_t ce = a.check_every > 0 ? a.check_every : 1;
@@ -220,6 +222,10 @@ __global__ void __launch_bounds__(kWgThreads) wg_solve_kernel(SolveArgs a) {
     const int nJ = (int)(a.col_off[j + 1] - c0);
     const TP* __restrict__ P = Acol + a.ldc * c0;  // (r, c) at c * ldc + r
     colsum_colmajor(P, m, a.ldc, nJ, z, v, red);
+    if (a.g) {  // refinement: project onto {A^T z = g}
+      for (int c = tid; c < nJ; c += T) v[c] -= a.g[c0 + c];
+      __syncthreads();
+    }
     const double cc = a.coef_col[j];
     for (int64_t r = tid; r < m; r += T) {
       double acc = 0.0;
@@ -255,6 +261,8 @@ __global__ void __launch_bounds__(kWgThreads) wg_solve_kernel(SolveArgs a) {
       for (int l = 0; l < nI; ++l) acc += widen(col[l]) * u[l];
       x[c] -= cr * acc;
     }
+    if (a.y_out)  // refinement: x - x_in = A^T y
+      for (int l = tid; l < nI; l += T) a.y_out[r0 + l] -= cr * u[l];
     __syncthreads();
     q_done = q + 1;
 
