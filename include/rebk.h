@@ -189,6 +189,55 @@ int rebk_philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                        uint64_t k0, uint64_t k1, int64_t count, uint64_t *out_dev, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Mixed precision with FP64 refinement.  The panels of the handle may hold
+ * rounded values (BF16, FP16, FP32); the iteration then converges to the
+ * least-squares solution of the rounded matrix.  This solve wins the
+ * accuracy back with an outer loop in FP64 on the augmented system of least
+ * squares  z + A x = b,  A^T z = 0,  x in range(A^T)  (its solution is
+ * z = (I - A A^+) b, the limit of Lemma 6, and x = A^+ b, Theorem 7):
+ *   f = b - z - A x,  g = -A^T z             (FP64, caller's A)
+ *   correction: Algorithm 1 on the panels with the z-step projecting onto
+ *     {A^T dz = g} (v = A_J^T dz - g_J) and the x-step solving A dx = f - dz,
+ *     from dz = f, dx = 0, for inner_iters iterations; y accumulates the
+ *     x-steps (dx = A_panels^T y)
+ *   z += dz,  x += A^T y                      (FP64, caller's A: x stays in
+ *                                              range(A^T) exactly)
+ * The inner block sequence continues one Philox stream: outer step q runs
+ * iterations q * inner_iters + 1 .. (q + 1) * inner_iters of the handle's
+ * seed and system 0.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const double *A_dev;      /* the FP64 matrix the handle was created from (or its exact
+                                 values), m x n row-major with leading dimension lda (required;
+                                 read-only, caller-owned, valid during the call) */
+    int64_t lda;
+    const double *b_dev;      /* right-hand side, m entries (required) */
+    const double *x0_dev;     /* starting x in range(A^T), n entries; NULL means 0 */
+    const double *x_ref_dev;  /* if not NULL, stop when ||x - x_ref|| / ||x_ref|| < tol; else
+                                 when ||f|| <= tol ||b|| and ||g|| <= tol ||A||_F ||b|| */
+    double tol;               /* tested before every outer step and after the last one */
+    int64_t inner_iters;      /* REBK iterations per correction solve (> 0) */
+    int32_t max_outer;        /* outer steps at most (>= 0) */
+    int32_t kernel;           /* rebk_kernel_t of the inner solves */
+    int32_t grid_wgs;         /* as in rebk_solve_opts_t */
+    double *x_out_dev;        /* result x, n entries (required) */
+    double *z_out_dev;        /* result z, m entries, or NULL */
+    double *err_trace;        /* host, max_outer + 1 entries, or NULL: the tested quantity
+                                 (relative error, or max of the two relative residuals) before
+                                 each outer step; entries after the last test are left as is */
+} rebk_refine_opts_t;
+
+/*
+ * Solve by FP64 refinement around REBK (see above).  res (host, may be
+ * NULL): status (REBK_OK when the stop rule held, else REBK_NOT_CONVERGED),
+ * iterations = inner iterations in total, rel_err = the last tested
+ * quantity, time_ms = device time of the whole loop.  Errors:
+ * REBK_ERR_INVALID (bad options or sizes), REBK_ERR_OOM, REBK_ERR_HIP,
+ * REBK_ERR_TIMEOUT.  Synchronizes the stream once per outer step.
+ */
+int rebk_solve_refined(rebk_handle_t h, const rebk_refine_opts_t *opts, rebk_result_t *res);
+
+/* ------------------------------------------------------------------------
  * Batched solves: many independent systems, each with several right-hand
  * sides, in one launch.  Every right-hand side is an exact REBK run
  * (Algorithm 1) with z^0 = b and x^0 = x0 (or 0); the right-hand sides of

@@ -182,6 +182,38 @@ class Solver:
             out["i"] = ti[: r.iterations]
         return out
 
+    def solve_refined(self, A64: torch.Tensor, b: torch.Tensor, *, x0=None, x_ref=None, tol: float = 1e-10,
+                      inner_iters: int = 1000, max_outer: int = 20, kernel: str = "auto", grid_wgs: int = 0,
+                      x_out=None, z_out=None):
+        """``rebk_solve_refined``: FP64 refinement of the augmented system around REBK on this
+        solver's panels.  A64 is the FP64 matrix (CUDA, row-major).  Returns dict(x, z, result,
+        err_trace (numpy, one entry per tested outer step))."""
+        if not (A64.is_cuda and A64.dtype == torch.float64 and A64.dim() == 2 and A64.stride(1) == 1
+                and tuple(A64.shape) == (self.m, self.n)):
+            raise ValueError("A64 must be a row-major CUDA float64 tensor of the solver's shape")
+        x = x_out if x_out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        z = z_out if z_out is not None else torch.empty(self.m, dtype=torch.float64, device=self.device)
+        trace = np.full(int(max_outer) + 1, np.nan)
+        o = N.RefineOpts()
+        o.A_dev = ctypes.c_void_p(A64.data_ptr())
+        o.lda = int(A64.stride(0))
+        o.b_dev = _dev_ptr(b, self.m, "b")
+        o.x0_dev = _dev_ptr(x0, self.n, "x0")
+        o.x_ref_dev = _dev_ptr(x_ref, self.n, "x_ref")
+        o.tol = float(tol)
+        o.inner_iters = int(inner_iters)
+        o.max_outer = int(max_outer)
+        o.kernel = N.KERNELS[kernel]
+        o.grid_wgs = int(grid_wgs)
+        o.x_out_dev = _dev_ptr(x, self.n, "x_out")
+        o.z_out_dev = _dev_ptr(z, self.m, "z_out")
+        o.err_trace = trace.ctypes.data_as(ctypes.c_void_p)
+        res = N.Result()
+        code = N.load().rebk_solve_refined(self._h, ctypes.byref(o), ctypes.byref(res))
+        N.check(code, "rebk_solve_refined")
+        r = self._result(res)
+        return {"x": x, "z": z, "result": r, "err_trace": trace[~np.isnan(trace)]}
+
     @staticmethod
     def _result(res: "N.Result") -> SolveResult:
         return SolveResult(status=N.STATUS_NAMES.get(res.status, str(res.status)), code=int(res.status),

@@ -40,6 +40,14 @@ class SolveOpts(ctypes.Structure):
     ]
 
 
+class RefineOpts(ctypes.Structure):
+    _fields_ = [
+        ("A_dev", P), ("lda", I64), ("b_dev", P), ("x0_dev", P), ("x_ref_dev", P), ("tol", F64),
+        ("inner_iters", I64), ("max_outer", I32), ("kernel", I32), ("grid_wgs", I32),
+        ("x_out_dev", P), ("z_out_dev", P), ("err_trace", P),
+    ]
+
+
 class BatchOpts(ctypes.Structure):
     _fields_ = [
         ("nrhs", P), ("b_dev", P), ("x0_dev", P), ("x_ref_dev", P), ("x_out_dev", P), ("z_out_dev", P),
@@ -63,6 +71,7 @@ SIGNATURES = {
     "rebk_get_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 6),
     "rebk_sample_blocks": (ctypes.c_int, [P, U64, I64, I64, P, P]),
     "rebk_philox4x64_10": (ctypes.c_int, [U64, U64, U64, U64, U64, U64, I64, P, P]),
+    "rebk_solve_refined": (ctypes.c_int, [P, ctypes.POINTER(RefineOpts), ctypes.POINTER(Result)]),
     "rebk_batch_create": (ctypes.c_int, [ctypes.POINTER(P), I32, P, P, P]),
     "rebk_batch_destroy": (None, [P]),
     "rebk_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(BatchOpts), P, ctypes.POINTER(F64)]),

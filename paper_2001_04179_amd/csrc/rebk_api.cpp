@@ -952,3 +952,143 @@ int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t* o, int64_t prob
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ FP64 refinement around REBK
+
+namespace {
+
+struct DevBuffers {  // device scratch of one call, freed on every return path
+  std::vector<void*> ptrs;
+  ~DevBuffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  double* get(size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (count > 0 ? count : 1) * sizeof(double)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return (double*)p;
+  }
+};
+
+// sum of squares of v (len entries) on the device, partial sums added on the host in order
+int dev_sumsq(rebk_handle* h, const double* v, int64_t len, double* out) {
+  HIP_TRY(rebk::launch_sumsq(v, len, h->partials, h->nparts, h->stream));
+  return host_sum(h, h->partials, h->nparts, out);
+}
+
+}  // namespace
+
+extern "C" int rebk_solve_refined(rebk_handle_t h, const rebk_refine_opts_t* o, rebk_result_t* res) {
+  g_err[0] = 0;
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (!o) return fail(REBK_ERR_INVALID, "opts is NULL");
+  if (!o->A_dev || !o->b_dev || !o->x_out_dev) return fail(REBK_ERR_INVALID, "A, b and x_out are required");
+  if (o->lda < h->n) return fail(REBK_ERR_INVALID, "lda must be at least n");
+  if (o->inner_iters <= 0) return fail(REBK_ERR_INVALID, "inner_iters must be positive");
+  if (o->max_outer < 0) return fail(REBK_ERR_INVALID, "max_outer must be non-negative");
+  if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
+  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel");
+  const int64_t m = h->m, n = h->n;
+  hipStream_t st = h->stream;
+  DevBuffers buf;
+  double* f = buf.get(m);
+  double* g = buf.get(n);
+  double* dz = buf.get(m);
+  double* dx = buf.get(n);
+  double* dy = buf.get(m);
+  double* partial = buf.get((size_t)rebk::refine_chunks(m) * n);
+  double* z = o->z_out_dev ? o->z_out_dev : buf.get(m);
+  if (!f || !g || !dz || !dx || !dy || !partial || !z) return fail(REBK_ERR_OOM, "cannot allocate refinement scratch");
+  double* x = o->x_out_dev;
+
+  double b2 = 0.0, a2 = 0.0, xr2 = 0.0;
+  int rc = dev_sumsq(h, o->b_dev, m, &b2);
+  if (rc != REBK_OK) return rc;
+  HIP_TRY(rebk::launch_sumsq_matrix(o->A_dev, o->lda, m, n, h->partials, h->nparts, st));
+  rc = host_sum(h, h->partials, h->nparts, &a2);
+  if (rc != REBK_OK) return rc;
+  if (o->x_ref_dev) {
+    rc = dev_sumsq(h, o->x_ref_dev, n, &xr2);
+    if (rc != REBK_OK) return rc;
+    if (!(xr2 > 0.0) || !std::isfinite(xr2)) return fail(REBK_ERR_INVALID, "x_ref must be non-zero and finite");
+  }
+  const double bn = std::sqrt(b2), an = std::sqrt(a2);
+  if (o->x0_dev) {
+    if (o->x0_dev != x) HIP_TRY(hipMemcpyAsync(x, o->x0_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), st));
+  }
+  HIP_TRY(hipMemcpyAsync(z, o->b_dev, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipEventRecord(h->ev0, st));
+
+  rebk_result_t r{};
+  r.status = REBK_NOT_CONVERGED;
+  int used = 0;
+  for (int64_t q = 0;; ++q) {
+    // residuals of the augmented system: f = b - z - A x, g = -A^T z
+    HIP_TRY(rebk::launch_resid_f(o->A_dev, o->lda, m, n, o->b_dev, z, x, f, st));
+    HIP_TRY(rebk::launch_gemv_t(o->A_dev, o->lda, m, n, z, -1.0, 0.0, g, nullptr, partial, st));
+    double e = 0.0;
+    bool ok = false;
+    if (o->x_ref_dev) {
+      double e2 = 0.0;
+      HIP_TRY(rebk::launch_err2(x, o->x_ref_dev, n, h->partials, h->nparts, st));
+      rc = host_sum(h, h->partials, h->nparts, &e2);
+      if (rc != REBK_OK) return rc;
+      e = std::sqrt(e2) / std::sqrt(xr2);
+      ok = e < o->tol;
+    } else {
+      double f2 = 0.0, g2 = 0.0;
+      rc = dev_sumsq(h, f, m, &f2);
+      if (rc == REBK_OK) rc = dev_sumsq(h, g, n, &g2);
+      if (rc != REBK_OK) return rc;
+      const double rf = std::sqrt(f2) / (bn > 0.0 ? bn : 1.0);
+      const double rg = std::sqrt(g2) / (an * bn > 0.0 ? an * bn : 1.0);
+      e = rf > rg ? rf : rg;
+      ok = rf <= o->tol && rg <= o->tol;
+    }
+    if (o->err_trace) o->err_trace[q] = e;
+    r.rel_err = e;
+    if (!std::isfinite(e)) {
+      r.status = REBK_DIVERGED;
+      break;
+    }
+    if (ok) {
+      r.status = REBK_OK;
+      break;
+    }
+    if (q >= o->max_outer) break;
+    // correction: REBK on (f, g) from dz = f, dx = 0, the Philox stream continuing at q * inner
+    rebk::SolveArgs a = base_args(h);
+    a.b = f;
+    a.z_in = f;
+    a.x_in = nullptr;
+    a.x_out = dx;
+    a.z_out = dz;
+    a.g = g;
+    a.y_out = dy;
+    a.x_ref = nullptr;
+    a.tol = 0.0;
+    a.k0 = q * o->inner_iters;
+    a.max_iter = o->inner_iters;
+    a.check_every = o->inner_iters;
+    rc = run_iterations(h, a, o->kernel, o->grid_wgs, &used);
+    if (rc != REBK_OK) return rc;
+    rebk::DevStatus ds{};
+    HIP_TRY(hipMemcpyAsync(&ds, h->status_d, sizeof(ds), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ds.status == REBK_ERR_TIMEOUT) return fail(REBK_ERR_TIMEOUT, "grid barrier spin limit exceeded");
+    r.iterations += o->inner_iters;
+    // z += dz, x += A^T y
+    HIP_TRY(rebk::launch_axpy(z, dz, m, st));
+    HIP_TRY(rebk::launch_gemv_t(o->A_dev, o->lda, m, n, dy, 1.0, 1.0, x, nullptr, partial, st));
+  }
+  HIP_TRY(hipEventRecord(h->ev1, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  r.kernel = used;
+  r.time_ms = ms;
+  if (res) *res = r;
+  return r.status;
+}

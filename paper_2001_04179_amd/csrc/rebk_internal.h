@@ -135,6 +135,16 @@ hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, 
 size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads);
 hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st);
 hipError_t batch_max_blocks(int panel_dtype, int threads, size_t lds_bytes, int* blocks_per_cu);
+// refinement kernels (FP64, caller's row-major A with leading dimension lda)
+int64_t refine_chunks(int64_t m);  // row chunks of the transposed product (partial: chunks x n doubles)
+hipError_t launch_resid_f(const double* A, int64_t lda, int64_t m, int64_t n, const double* b, const double* z,
+                          const double* x, double* f, hipStream_t st);
+hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* v, double alpha,
+                         double beta, double* out, double* sq, double* partial, hipStream_t st);
+hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t st);
+hipError_t launch_sumsq(const double* v, int64_t n, double* partials, int nparts, hipStream_t st);
+hipError_t launch_sumsq_matrix(const double* A, int64_t lda, int64_t m, int64_t n, double* partials, int nparts,
+                               hipStream_t st);
 hipError_t launch_err2(const double* x, const double* x_ref, int64_t n, double* partials, int nparts,
                        hipStream_t st);
 
