@@ -323,6 +323,22 @@ int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t *opts, int64_t p
                         int32_t *threads, int32_t *lds_budget, int32_t *max_tile, int32_t *xcd_order,
                         double *best_ms);
 
+/*
+ * Block constants of Section 2.2 for the stepsize (Remark 9: alpha = 1 / beta_max, and any
+ * 0 < alpha < 2 / beta_max converges):
+ *   beta_row[i] = ||A_{I_i,:}||_2^2 / ||A_{I_i,:}||_F^2   (s entries, host, may be NULL)
+ *   beta_col[j] = ||A_{:,J_j}||_2^2 / ||A_{:,J_j}||_F^2   (t entries, host, may be NULL)
+ *   *beta_max   = the largest of them                      (host, may be NULL)
+ * of the stored panel values.  Each block's Gram matrix of its shorter side d (at most 8192) is
+ * formed on the device in FP64; its largest eigenvalue is the Rayleigh quotient of a power
+ * iteration, stopped when it changes by at most rtol relative or after max_steps steps
+ * (*steps_max, may be NULL, receives the most steps any block took).  The quotient approaches
+ * the eigenvalue from below, at a rate set by the ratio of the two largest eigenvalues.
+ * Allocates sum d^2 doubles of scratch for the call.  Synchronizes the stream.
+ */
+int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol, double *beta_row, double *beta_col,
+                     double *beta_max, int32_t *steps_max);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *rebk_last_error(void);
 

@@ -217,3 +217,20 @@ def rebk_refine(A, A_stored, row_off, col_off, alpha, seed, b, *, x0=None, x_ref
     return {"x": x, "z": z, "err_trace": trace[:tested], "outer": int(outer[0]), "iterations": int(iters[0]),
             "err": float(err[0]), "status": int(st)}
 
+
+
+def block_betas(A, row_off, col_off):
+    """Block constants of Section 2.2: beta = ||B||_2^2 / ||B||_F^2 for every row block
+    A[I_i, :] and column block A[:, J_j], from the largest eigenvalue of the Gram matrix of the
+    block's shorter side (LAPACK, FP64) over its trace.  Returns (beta_row, beta_col)."""
+    A = _f64(A)
+
+    def beta(B):
+        G = B @ B.T if B.shape[0] <= B.shape[1] else B.T @ B
+        tr = float(np.trace(G))
+        return float(np.linalg.eigvalsh(G)[-1]) / tr if tr > 0 else 0.0
+
+    ro, co = _i64(row_off), _i64(col_off)
+    br = np.array([beta(A[ro[i]:ro[i + 1], :]) for i in range(len(ro) - 1)])
+    bc = np.array([beta(A[:, co[j]:co[j + 1]]) for j in range(len(co) - 1)])
+    return br, bc

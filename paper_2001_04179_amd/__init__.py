@@ -182,6 +182,21 @@ class Solver:
             out["i"] = ti[: r.iterations]
         return out
 
+    def block_betas(self, max_steps: int = 5000, rtol: float = 1e-13):
+        """``rebk_block_betas``: (beta_row (s,), beta_col (t,), beta_max, steps) of the stored panels."""
+        br = np.zeros(self.s)
+        bc = np.zeros(self.t)
+        bm = ctypes.c_double()
+        steps = ctypes.c_int32()
+        N.check(N.load().rebk_block_betas(self._h, int(max_steps), float(rtol), br.ctypes.data_as(ctypes.c_void_p),
+                                          bc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(bm), ctypes.byref(steps)),
+                "rebk_block_betas")
+        return br, bc, float(bm.value), int(steps.value)
+
+    def suggest_alpha(self, c: float = 1.0, **kw) -> float:
+        """alpha = c / beta_max (Remark 9: c = 1 is the paper's default; any 0 < c < 2 converges)."""
+        return float(c) / self.block_betas(**kw)[2]
+
     def solve_refined(self, A64: torch.Tensor, b: torch.Tensor, *, x0=None, x_ref=None, tol: float = 1e-10,
                       inner_iters: int = 1000, max_outer: int = 20, kernel: str = "auto", grid_wgs: int = 0,
                       x_out=None, z_out=None):

@@ -72,6 +72,7 @@ SIGNATURES = {
     "rebk_sample_blocks": (ctypes.c_int, [P, U64, I64, I64, P, P]),
     "rebk_philox4x64_10": (ctypes.c_int, [U64, U64, U64, U64, U64, U64, I64, P, P]),
     "rebk_solve_refined": (ctypes.c_int, [P, ctypes.POINTER(RefineOpts), ctypes.POINTER(Result)]),
+    "rebk_block_betas": (ctypes.c_int, [P, I32, F64, P, P, ctypes.POINTER(F64), ctypes.POINTER(I32)]),
     "rebk_batch_create": (ctypes.c_int, [ctypes.POINTER(P), I32, P, P, P]),
     "rebk_batch_destroy": (None, [P]),
     "rebk_batch_solve": (ctypes.c_int, [P, ctypes.POINTER(BatchOpts), P, ctypes.POINTER(F64)]),

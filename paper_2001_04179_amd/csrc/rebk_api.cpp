@@ -1092,3 +1092,98 @@ extern "C" int rebk_solve_refined(rebk_handle_t h, const rebk_refine_opts_t* o, 
   if (res) *res = r;
   return r.status;
 }
+
+// ------------------------------------------------------------------ block constants beta
+
+extern "C" int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol, double* beta_row, double* beta_col,
+                                double* beta_max, int32_t* steps_max) {
+  g_err[0] = 0;
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (max_steps <= 0) return fail(REBK_ERR_INVALID, "max_steps must be positive");
+  if (!(rtol >= 0.0)) return fail(REBK_ERR_INVALID, "rtol must be non-negative");
+  const int64_t m = h->m, n = h->n;
+  // one pass per panel layout: row blocks (Arow: entry (l, c) of block i at n*r0 + c*nI + l),
+  // column blocks (Acol: entry (r, c) of block j at ldc*c0 + c*ldc + r)
+  struct Pass {
+    const void* P;
+    std::vector<rebk::GramDesc> desc;
+    double* out;
+  };
+  std::vector<Pass> passes(2);
+  passes[0].P = h->Arow;
+  passes[0].out = beta_row;
+  passes[1].P = h->Acol;
+  passes[1].out = beta_col;
+  int64_t gram_total = 0;
+  int32_t max_d = 0;
+  auto add = [&](Pass& p, int64_t base, int64_t rows, int64_t cols, int64_t s_row, int64_t s_col) {
+    // block of rows x cols with entry (r, c) at base + r * s_row + c * s_col; Gram of the shorter side
+    rebk::GramDesc d{};
+    d.base = base;
+    if (rows <= cols) {
+      d.d = (int32_t)rows; d.L = cols; d.sa = s_row; d.st = s_col;
+    } else {
+      d.d = (int32_t)cols; d.L = rows; d.sa = s_col; d.st = s_row;
+    }
+    d.gram = gram_total;
+    gram_total += (int64_t)d.d * d.d;
+    if (d.d > max_d) max_d = d.d;
+    p.desc.push_back(d);
+  };
+  for (int64_t i = 0; i < h->s; ++i) {
+    const int64_t r0 = h->row_off[i], nI = h->row_off[i + 1] - r0;
+    add(passes[0], n * r0, nI, n, 1, nI);
+  }
+  for (int64_t j = 0; j < h->t; ++j) {
+    const int64_t c0 = h->col_off[j], nJ = h->col_off[j + 1] - c0;
+    add(passes[1], h->ldc * c0, m, nJ, 1, h->ldc);
+  }
+  if (max_d > 8192) return fail(REBK_ERR_INVALID, "blocks whose shorter side exceeds 8192 are not supported");
+  DevBuffers buf;
+  double* gram = buf.get((size_t)gram_total);
+  if (!gram) return fail(REBK_ERR_OOM, "cannot allocate %lld Gram entries", (long long)gram_total);
+  hipStream_t st = h->stream;
+  double bmax = 0.0;
+  int32_t smax = 0;
+  for (Pass& p : passes) {
+    const int nb = (int)p.desc.size();
+    std::vector<int32_t> tb, ta1, ta2;
+    for (int b = 0; b < nb; ++b) {
+      const int D = p.desc[b].d;
+      for (int a1 = 0; a1 < D; a1 += 16)
+        for (int a2 = 0; a2 < D; a2 += 16) {
+          tb.push_back(b);
+          ta1.push_back(a1);
+          ta2.push_back(a2);
+        }
+    }
+    const size_t nt = tb.size();
+    rebk::GramDesc* desc_d = (rebk::GramDesc*)buf.get((nb * sizeof(rebk::GramDesc) + 7) / 8);
+    int32_t* tiles_d = (int32_t*)buf.get((3 * nt * sizeof(int32_t) + 7) / 8);
+    double* lam_d = buf.get(nb);
+    double* tr_d = buf.get(nb);
+    int32_t* steps_d = (int32_t*)buf.get((nb * sizeof(int32_t) + 7) / 8);
+    if (!desc_d || !tiles_d || !lam_d || !tr_d || !steps_d) return fail(REBK_ERR_OOM, "cannot allocate beta scratch");
+    HIP_TRY(hipMemcpyAsync(desc_d, p.desc.data(), nb * sizeof(rebk::GramDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tiles_d, tb.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tiles_d + nt, ta1.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tiles_d + 2 * nt, ta2.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(rebk::launch_gram(p.P, h->panel_dtype, desc_d, (int)nt, tiles_d, tiles_d + nt, tiles_d + 2 * nt, gram, st));
+    HIP_TRY(rebk::launch_power(desc_d, nb, max_d, gram, max_steps, rtol, lam_d, tr_d, steps_d, st));
+    std::vector<double> lam(nb), tr(nb);
+    std::vector<int32_t> steps(nb);
+    HIP_TRY(hipMemcpyAsync(lam.data(), lam_d, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(tr.data(), tr_d, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(steps.data(), steps_d, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < nb; ++b) {
+      const double beta = tr[b] > 0.0 ? lam[b] / tr[b] : 0.0;
+      if (p.out) p.out[b] = beta;
+      if (beta > bmax) bmax = beta;
+      if (steps[b] > smax) smax = steps[b];
+    }
+  }
+  if (beta_max) *beta_max = bmax;
+  if (steps_max) *steps_max = smax;
+  return REBK_OK;
+}

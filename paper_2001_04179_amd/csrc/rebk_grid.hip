@@ -94,8 +94,9 @@ __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int max_
   L.NR = (int)((m + G - 1) / G);
   L.NC = (int)((n + G - 1) / G);
   L.dbl = 4 * (size_t)L.NR + 2 * (size_t)L.NC + (size_t)max_nJ + (size_t)max_nI + (size_t)threads + 8;
-  L.slabC = (size_t)L.NR * max_nJ;
-  L.slabR = row_lds ? (size_t)L.NC * max_nI : 0;
+  // slab buffers padded to 8 entries, so every buffer starts 16-byte aligned in LDS
+  L.slabC = ((size_t)L.NR * max_nJ + 7) / 8 * 8;
+  L.slabR = row_lds ? ((size_t)L.NC * max_nI + 7) / 8 * 8 : 0;
   return L;
 }
 
@@ -128,25 +129,32 @@ __device__ __forceinline__ double group_sum(double v, int width) {
 
 constexpr int kRing = 128;  // block draws kept ahead (relative iteration q in slot (q - 1) & 127)
 
-// Copy `runs` runs of `len` panel elements (run r starts at src + r * stride, lands at
-// dst + r * len) into LDS.  Waves 1..3 issue global_load_lds copies (one dword per lane, up to 256
-// bytes per wave instruction; asynchronous, complete for the issuing wave after
-// s_waitcnt vmcnt(0)).  Returns false when the runs are not whole 4-byte-aligned dwords (2-byte
-// panels), in which case nothing was issued.
+// Whether `runs` runs of `len` panel elements (run r at src + r * stride, landing at dst + r * len)
+// are whole 4-byte-aligned dwords at both ends, as the LDS copy below needs (always true for 4- and
+// 8-byte panels; for 2-byte panels it depends on the offsets).  The same for every thread.
 template <typename TP>
-__device__ __forceinline__ bool dma_runs(const TP* src, int64_t stride, int runs, int len, TP* dst) {
-  if (sizeof(TP) < 4) return false;
+__device__ __forceinline__ bool dma_ok(const TP* src, int64_t stride, int runs, int len, const TP* dst) {
+  if (sizeof(TP) >= 4 || runs <= 0) return true;
+  return (((uintptr_t)src | (uintptr_t)dst) & 3) == 0 && (len & 1) == 0 && (runs == 1 || (stride & 1) == 0);
+}
+
+// Copy those runs into LDS.  Waves 1..3 issue global_load_lds copies of 256-byte pieces (one
+// dword per lane), the pieces of all runs spread over the three waves; the copies are
+// asynchronous and complete for the issuing wave after s_waitcnt vmcnt(0).
+template <typename TP>
+__device__ __forceinline__ void dma_runs(const TP* src, int64_t stride, int runs, int len, TP* dst) {
   const int wave = (int)(threadIdx.x >> 6) - 1, lane = (int)(threadIdx.x & 63);
   const int bytes = len * (int)sizeof(TP);
-  for (int r = wave; r < runs; r += 3) {
+  const int pieces = (bytes + 255) / 256;
+  const int total = runs * pieces;
+  for (int p = wave; p < total; p += 3) {
+    const int r = p / pieces, off = (p - r * pieces) * 256;
     const char* s = (const char*)(src + (int64_t)r * stride);
     char* d = (char*)(dst + (size_t)r * len);
-    for (int off = 0; off < bytes; off += 256)
-      if (off + lane * 4 < bytes)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off + lane * 4),
-                                         (__attribute__((address_space(3))) void*)(d + off), 4, 0, 0);
+    if (off + lane * 4 < bytes)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off + lane * 4),
+                                       (__attribute__((address_space(3))) void*)(d + off), 4, 0, 0);
   }
-  return true;
 }
 
 template <typename TP, bool RowLds>
@@ -275,12 +283,14 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     const double cr = s_cr[sl];
     for (int64_t l = lo + tid; l < hi; l += T) yv[l - r0] -= cr * u[l - rI];
   };
-  auto copy_plain = [&](const Src& sr, TP* dC, TP* dR) {  // every thread, ordinary loads
-    for (int e = tid; e < sr.runs * nr; e += T) {
-      const int c = e / nr, q = e - c * nr;
-      dC[e] = sr.c[(int64_t)c * a.ldc + q];
-    }
-    for (int e = tid; e < sr.lr; e += T) dR[e] = sr.r[e];
+  auto copy_plain = [&](const Src& sr, TP* dC, TP* dR) {  // every thread, ordinary loads; NULL: skip
+    if (dC)
+      for (int e = tid; e < sr.runs * nr; e += T) {
+        const int c = e / nr, q = e - c * nr;
+        dC[e] = sr.c[(int64_t)c * a.ldc + q];
+      }
+    if (dR)
+      for (int e = tid; e < sr.lr; e += T) dR[e] = sr.r[e];
   };
 
   // One grid-wide reduction of this round's partial vectors (entries [0, nq), [MJ, MJ + np) and,
@@ -345,10 +355,11 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     const Src sr = slab_src(qc, qr);
     TP* dC = slabC + (size_t)bufC * L.slabC;
     TP* dR = RowLds ? slabR + (size_t)bufR * L.slabR : slabR;
-    bool dma = false;
+    const bool okC = dma_ok(sr.c, a.ldc, sr.runs, nr, dC);
+    const bool okR = dma_ok(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
     if (tid >= 64) {  // waves 1..3: start the copies of the next slabs straight into LDS
-      dma = dma_runs(sr.c, a.ldc, sr.runs, nr, dC);
-      dma_runs(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
+      if (okC) dma_runs(sr.c, a.ldc, sr.runs, nr, dC);
+      if (okR) dma_runs(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
     }
     const unsigned long long* Gall = gs.gsum + (size_t)(epoch % kSumRing) * NG * E * 2;
     // wave 0 watches one entry of every group (the highest one reduced this round)
@@ -402,9 +413,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       else if (e < MJ + MI) u[e - MJ] = s;
       else s_err2 = s;
     }
-    // 2-byte panels are copied with ordinary loads; then wait for the copies this wave started
-    if (sizeof(TP) < 4) copy_plain(sr, dC, dR);
-    (void)dma;
+    // slabs of 2-byte panels that are not whole aligned dwords are copied with ordinary loads;
+    // then wait for the copies this wave started
+    if (!okC || !okR) copy_plain(sr, okC ? nullptr : dC, okR ? nullptr : dR);
     wait_mem();
     if (!ok) s_ok = 0;
     __syncthreads();
@@ -437,8 +448,13 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       double acc = 0.0;
       if (cc < nc) {
         const TP* col = Sl + (size_t)cc * nI;
+        if constexpr (RowLds) {
 #pragma unroll 4
-        for (int l = sub; l < nI; l += tpc) acc += widen(col[l]) * u[l];
+          for (int l = sub; l < nI; l += tpc) acc += widen(col[l]) * u[l];
+        } else {  // from HBM: more loads in flight
+#pragma unroll 16
+          for (int l = sub; l < nI; l += tpc) acc += widen(col[l]) * u[l];
+        }
       }
       acc = group_sum(acc, tpc);
       if (cc < nc && sub == 0) x[cc] -= coef * acc;
@@ -528,8 +544,13 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       const int64_t rI = s_r0[sk];
       for (int l = tid; l < nIk; l += T) {
         double acc = 0.0;
+        if constexpr (RowLds) {
 #pragma unroll 4
-        for (int cc = 0; cc < nc; ++cc) acc += widen(Sr[cc * nIk + l]) * x[cc];
+          for (int cc = 0; cc < nc; ++cc) acc += widen(Sr[cc * nIk + l]) * x[cc];
+        } else {  // from HBM: more loads in flight
+#pragma unroll 16
+          for (int cc = 0; cc < nc; ++cc) acc += widen(Sr[cc * nIk + l]) * x[cc];
+        }
         const int64_t gl = rI + l;
         if (gl >= r0 && gl < r1) acc += z[gl - r0] - bl[gl - r0];
         st_tagged(P, E, MJ + l, acc, ep);

@@ -135,6 +135,21 @@ hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, 
 size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads);
 hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st);
 hipError_t batch_max_blocks(int panel_dtype, int threads, size_t lds_bytes, int* blocks_per_cu);
+// Gram matrix of one block's shorter side: G[a1][a2] = sum_{t < L} X(a1, t) X(a2, t) with
+// X(a, t) = panel[base + a * sa + t * st]; G stored row-major (d x d) at gram offset `gram`.
+struct GramDesc {
+  int64_t base;
+  int64_t L;
+  int64_t sa, st;
+  int64_t gram;
+  int32_t d;
+  int32_t pad;
+};
+hipError_t launch_gram(const void* P, int panel_dtype, const GramDesc* desc, int ntiles, const int32_t* tile_block,
+                       const int32_t* tile_a1, const int32_t* tile_a2, double* gram, hipStream_t st);
+hipError_t launch_power(const GramDesc* desc, int nblocks, int max_d, const double* gram, int max_steps, double rtol,
+                        double* lam, double* trace, int32_t* steps, hipStream_t st);
+
 // refinement kernels (FP64, caller's row-major A with leading dimension lda)
 int64_t refine_chunks(int64_t m);  // row chunks of the transposed product (partial: chunks x n doubles)
 hipError_t launch_resid_f(const double* A, int64_t lda, int64_t m, int64_t n, const double* b, const double* z,

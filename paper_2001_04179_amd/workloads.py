@@ -166,6 +166,15 @@ def rank1500_20000x2000(rng_seed=1002, seed=0, scale: int = 1) -> System:
                           fro2_target=float(m))
 
 
+def rank1200_2000x50000(rng_seed=1003, seed=0, scale: int = 1) -> System:
+    """Underdetermined rank-deficient A = U V (U 2000 x 1200, V 1200 x 50000, N(0,1), not
+    normalised); b = A x* + r, r in null(A^T) with ||r|| = 0.1 ||A x*||; 20 row blocks of 100
+    rows, 500 column blocks of 100 columns; alpha = 1 / beta_max.  ``scale`` > 1 divides the
+    dimensions (not the block sizes)."""
+    m, n, r = 2000 // scale, 50000 // scale, 1200 // scale
+    return factor_product(m, n, r, rng_seed=rng_seed, noise=0.1, row_tau=100, col_tau=100, alpha_c=1.0, seed=seed)
+
+
 @dataclass
 class BatchSystem:
     """One system of a batch with several right-hand sides (rows of B, X_ref)."""
