@@ -52,9 +52,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-iters", type=int, default=2000)
     p.add_argument("--scale", type=int, default=1, help="divide the problem dimensions (quick checks only)")
-    p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched", "mixed"],
+    p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched", "mixed", "sweeps"],
                    help="rank1500: the 20000 x 2000 single system; batched: 256 systems x 16 right-hand sides; "
                         "mixed: the 2000 x 50000 rank-1200 system, BF16/FP16 panels with FP64 refinement")
+    p.add_argument("--sweep-scale", type=int, default=4,
+                   help="divide the block-size sweep's 20000 x 5000 systems by this factor")
     p.add_argument("--mixed-inner", default="500,1000,2000,4000",
                    help="inner iterations per refinement step to try")
     p.add_argument("--batch-panels", default="f32", choices=["f64", "f32", "bf16", "f16"])
@@ -399,6 +401,67 @@ def bench_mixed(args):
     print(json.dumps(line))
 
 
+def bench_sweeps(args):
+    """Paper-shaped sweeps on the GPU with the paper's stop rule ||x - A^+ b|| <= 1e-5 (Section 3):
+    stepsize alpha = c / beta_max (Figure 1: Type I 500 x 250, r 150, kappa 2, and Type II
+    randn(500, 250), tau = 10); block size tau (Figure 2: Type I r = 0.9 n, kappa 2 and Type II at
+    20000 x 5000 / scale, alpha = 1.75 / beta_max); rows m (Figure 3: n = 500, Type I r 250 kappa 2
+    and Type II, tau = 10, alpha = 1.75 / beta_max) with REK (tau = 1, alpha = 1) as reference.
+    beta_max comes from the library's block constants (rebk_block_betas).  Prints one JSON line."""
+    import torch
+    import paper_2001_04179_amd as rebk
+    from paper_2001_04179_amd import workloads as W
+    dev = torch.device("cuda:0")
+
+    def run(S, c=None, alpha=None, tau=None, label=""):
+        A_d = torch.from_numpy(S.A).to(dev)
+        sv = rebk.Solver(A_d, S.row_off, S.col_off, 1.0, 0, panel_dtype="f64")
+        _, _, bmax, _ = sv.block_betas(max_steps=20000, rtol=1e-12)
+        a = alpha if alpha is not None else c / bmax
+        sv.close()
+        sv = rebk.Solver(A_d, S.row_off, S.col_off, a, 0, panel_dtype="f64")
+        xr = torch.from_numpy(S.x_ref).to(dev)
+        tol = 1e-5 / float(np.linalg.norm(S.x_ref))  # absolute 1e-5 as a relative tolerance
+        o = sv.solve_ex(torch.from_numpy(S.b).to(dev), x_ref=xr, tol=tol, check_every=1, max_iter=3_000_000)
+        torch.cuda.synchronize()
+        sv.close()
+        r = o["result"]
+        return {"label": label, "m": S.A.shape[0], "n": S.A.shape[1], "tau": tau, "c": c, "alpha": a,
+                "beta_max": bmax, "iterations": r.iterations, "ms": r.time_ms, "status": r.status, "kernel": r.kernel}
+
+    out = {"figure1_alpha": [], "figure2_tau": [], "figure3_m": []}
+    for kind in ("type1", "type2"):
+        S = (W.type1(500, 250, 150, 2.0, rng_seed=11, row_tau=10, col_tau=10) if kind == "type1"
+             else W.type2(500, 250, rng_seed=12, row_tau=10, col_tau=10))
+        for c in (0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.25, 2.5, 2.62):
+            e = run(S, c=c, tau=10, label=kind)
+            out["figure1_alpha"].append(e)
+            print(f"# fig1 {json.dumps(e)}", file=sys.stderr, flush=True)
+    sc = args.sweep_scale
+    m2, n2 = 20000 // sc, 5000 // sc
+    for kind in ("type1", "type2"):
+        for tau in (5, 10, 20, 50, 100, 200):
+            S = (W.type1(m2, n2, int(0.9 * n2), 2.0, rng_seed=21, row_tau=tau, col_tau=tau) if kind == "type1"
+                 else W.type2(m2, n2, rng_seed=22, row_tau=tau, col_tau=tau))
+            e = run(S, c=1.75, tau=tau, label=kind)
+            out["figure2_tau"].append(e)
+            print(f"# fig2 {json.dumps(e)}", file=sys.stderr, flush=True)
+    for kind in ("type1", "type2"):
+        for m in (2000, 6000, 10000, 14000, 20000):
+            S = (W.type1(m, 500, 250, 2.0, rng_seed=31, row_tau=10, col_tau=10) if kind == "type1"
+                 else W.type2(m, 500, rng_seed=32, row_tau=10, col_tau=10))
+            e = run(S, c=1.75, tau=10, label=kind)
+            out["figure3_m"].append(e)
+            print(f"# fig3 {json.dumps(e)}", file=sys.stderr, flush=True)
+            if m in (2000, 10000):  # REK: single rows and columns, alpha = 1 (Section 2)
+                Sr = (W.type1(m, 500, 250, 2.0, rng_seed=31, row_tau=1, col_tau=1) if kind == "type1"
+                      else W.type2(m, 500, rng_seed=32, row_tau=1, col_tau=1))
+                e = run(Sr, alpha=1.0, tau=1, label=kind + "-REK")
+                out["figure3_m"].append(e)
+                print(f"# fig3 {json.dumps(e)}", file=sys.stderr, flush=True)
+    print(json.dumps({"sweeps": out, "stop_rule": "||x - A^+ b|| <= 1e-5 (absolute)", "scale_figure2": sc}))
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -412,6 +475,9 @@ def main():
         return
     if args.workload == "mixed":
         bench_mixed(args)
+        return
+    if args.workload == "sweeps":
+        bench_sweeps(args)
         return
     import torch
     import paper_2001_04179_amd as rebk

@@ -79,7 +79,7 @@ typedef enum {
 
 /* Which kernel runs the iterations. */
 typedef enum {
-    REBK_KERNEL_AUTO = 0,     /* GRID for large blocks, WORKGROUP otherwise */
+    REBK_KERNEL_AUTO = 0,     /* WORKGROUP for tiny systems (m |J| + |I| n + 4 (m + n) <= 8192), GRID otherwise */
     REBK_KERNEL_WORKGROUP = 1,/* one workgroup runs the whole solve (small systems) */
     REBK_KERNEL_GRID = 2      /* one persistent cooperative grid, one grid barrier per iteration */
 } rebk_kernel_t;
