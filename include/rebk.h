@@ -286,6 +286,8 @@ typedef struct {
                                        (0: tuned, else 4) */
     int32_t xcd_order;              /* 1: dispatch the tasks of a system to one XCD (shared L2);
                                        0: plain longest-first order; -1: tuned (default 1) */
+    int32_t z0_from_x0;             /* 1: where x0 is given, start from z0 = b - A x0 (computed from
+                                       the stored panels) instead of z0 = b */
 } rebk_batch_opts_t;
 
 /* Result of one right-hand side of a batch. */
@@ -338,6 +340,59 @@ int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t *opts, int64_t p
  */
 int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol, double *beta_row, double *beta_col,
                      double *beta_max, int32_t *steps_max);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A network maps a right-hand side b to y; the start
+ * x0 = A^T y lies in range(A^T) and z0 = b - A x0 in b + range(A), the
+ * hypotheses of Theorem 7, so REBK from (x0, z0) still converges to A^+ b
+ * (plain REBK from x0 = 0, z0 = b is the fallback and the judge of its
+ * error).  The network is
+ *   h1 = relu(W1 (s b) + c1),  h2 = relu(W2 h1 + c2),  y = W3 h2 + c3
+ * (s: a scale of the input), trained with Adam (Kingma and Ba) on
+ *   loss = 1 / (2 batch) * sum over the batch ||A^T y - x_target||^2.
+ * Every product runs on the matrix cores with half-precision operands and
+ * FP32 accumulation; the weights have FP32 masters.  Batches are row-major
+ * (one right-hand side per row), batch a multiple of 64 up to max_batch.
+ * ------------------------------------------------------------------------ */
+typedef struct rebk_mlp *rebk_mlp_t;
+
+/*
+ * Create a network in_dim -> hidden -> hidden -> out_dim for the matrix A
+ * (A_dev: out_dim x n, FP64 row-major, copied in half precision; out_dim is
+ * m).  All sizes must be positive multiples of 64.  Weights start uniform in
+ * +-1/sqrt(fan_in) from Philox4x64-10 with the given seed, biases at zero.
+ * Errors: REBK_ERR_INVALID, REBK_ERR_OOM, REBK_ERR_HIP.
+ */
+int rebk_mlp_create(rebk_mlp_t *out, int32_t in_dim, int32_t hidden, const double *A_dev,
+                    int64_t out_dim, int64_t n, int32_t max_batch, uint64_t seed, void *stream);
+void rebk_mlp_destroy(rebk_mlp_t w);
+
+/* Copy parameters from / to host FP32 arrays (W1 hidden x in_dim, c1 hidden, W2 hidden x hidden,
+ * c2 hidden, W3 out_dim x hidden, c3 out_dim; row-major); NULL entries are skipped. */
+int rebk_mlp_set_params(rebk_mlp_t w, const float *W1, const float *c1, const float *W2,
+                        const float *c2, const float *W3, const float *c3);
+int rebk_mlp_get_params(rebk_mlp_t w, float *W1, float *c1, float *W2, float *c2, float *W3,
+                        float *c3);
+
+/* Inference: X0_dev (batch x n, FP64) = rows of A^T y for the rows of B_dev (batch x in_dim,
+ * FP64, scaled by b_scale); Y_dev (batch x out_dim, FP64) receives y if not NULL. */
+int rebk_mlp_forward(rebk_mlp_t w, const double *B_dev, int32_t batch, double b_scale,
+                     double *X0_dev, double *Y_dev);
+
+/* Gradients of the loss for the batch (B_dev as above, Xt_dev batch x n FP64 targets), kept in the
+ * network; *loss (host, may be NULL) receives the loss.  rebk_mlp_get_grads copies them to host
+ * FP32 arrays laid out like the parameters. */
+int rebk_mlp_grad(rebk_mlp_t w, const double *B_dev, const double *Xt_dev, int32_t batch,
+                  double b_scale, double *loss);
+int rebk_mlp_get_grads(rebk_mlp_t w, float *gW1, float *gc1, float *gW2, float *gc2, float *gW3,
+                       float *gc3);
+
+/* One Adam step with the kept gradients (beta1, beta2 in [0, 1), eps > 0). */
+int rebk_mlp_adam(rebk_mlp_t w, double lr, double beta1, double beta2, double eps);
+
+/* rebk_mlp_grad followed by rebk_mlp_adam(lr, 0.9, 0.999, 1e-8). */
+int rebk_mlp_train_step(rebk_mlp_t w, const double *B_dev, const double *Xt_dev, int32_t batch,
+                        double b_scale, double lr, double *loss);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *rebk_last_error(void);

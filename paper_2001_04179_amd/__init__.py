@@ -15,7 +15,8 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "SolveResult", "Batch", "philox4x64_10", "contiguous_offsets", "RebkError", "version"]
+__all__ = ["Solver", "SolveResult", "Batch", "WarmStart", "philox4x64_10", "contiguous_offsets", "RebkError",
+           "version"]
 
 RebkError = N.RebkError
 
@@ -267,7 +268,7 @@ class Batch:
             pass
 
     def _opts(self, B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget, max_tile,
-              xcd_order):
+              xcd_order, z0_from_x0=False):
         """B[s]: (nrhs_s, m_s) float64 CUDA tensors; x_ref / x0 (optional) and x_out: (nrhs_s, n_s)."""
         if len(B) != self.nsys:
             raise ValueError("one right-hand-side matrix per system")
@@ -305,10 +306,12 @@ class Batch:
         o.lds_budget = int(lds_budget)
         o.max_tile = int(max_tile)
         o.xcd_order = int(xcd_order)
+        o.z0_from_x0 = 1 if z0_from_x0 else 0
         return o, nrhs, keep
 
     def solve(self, B, *, x_ref=None, x0=None, max_iter: int = 100000, tol: float = 0.0, check_every: int = 0,
-              threads: int = 0, lds_budget: int = 0, max_tile: int = 0, xcd_order: int = -1, want_z: bool = False):
+              threads: int = 0, lds_budget: int = 0, max_tile: int = 0, xcd_order: int = -1, want_z: bool = False,
+              z0_from_x0: bool = False):
         """``rebk_batch_solve``.  Returns dict(x=[...], z=[...] or None, iterations, rel_err, status, tile
         (numpy arrays over all right-hand sides, system after system), time_ms, code)."""
         dev = self.solvers[0].device
@@ -317,7 +320,7 @@ class Batch:
         z_out = ([torch.empty((int(b.shape[0]), sv.m), dtype=torch.float64, device=dev)
                   for b, sv in zip(B, self.solvers)] if want_z else None)
         o, nrhs, keep = self._opts(B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget,
-                                   max_tile, xcd_order)
+                                   max_tile, xcd_order, z0_from_x0)
         total = sum(nrhs)
         res = (N.BatchRhs * total)()
         ms = ctypes.c_double(0.0)
@@ -348,6 +351,95 @@ class Batch:
         del keep
         return {"threads": th.value, "lds_budget": ld.value, "max_tile": tl.value, "xcd_order": xo.value,
                 "ms": ms.value}
+
+
+class WarmStart:
+    """``rebk_mlp_*``: the learned warm start network in_dim -> hidden -> hidden -> m for A (m x n,
+    CUDA float64).  forward(B) gives rows x0 = A^T y; grad / adam / train_step train it."""
+
+    NAMES = ("W1", "c1", "W2", "c2", "W3", "c3")
+
+    def __init__(self, A: torch.Tensor, in_dim: int, hidden: int = 512, max_batch: int = 256, seed: int = 0):
+        if not (A.is_cuda and A.dtype == torch.float64 and A.dim() == 2 and A.is_contiguous()):
+            raise ValueError("A must be a contiguous CUDA float64 matrix")
+        self.m, self.n = int(A.shape[0]), int(A.shape[1])
+        self.in_dim, self.hidden, self.max_batch = int(in_dim), int(hidden), int(max_batch)
+        self.device = A.device
+        w = ctypes.c_void_p()
+        N.check(N.load().rebk_mlp_create(ctypes.byref(w), self.in_dim, self.hidden, ctypes.c_void_p(A.data_ptr()),
+                                         self.m, self.n, self.max_batch, ctypes.c_uint64(int(seed)), _stream_ptr()),
+                "rebk_mlp_create")
+        self._w = w
+
+    def shapes(self):
+        h, i, m = self.hidden, self.in_dim, self.m
+        return {"W1": (h, i), "c1": (h,), "W2": (h, h), "c2": (h,), "W3": (m, h), "c3": (m,)}
+
+    def close(self):
+        if getattr(self, "_w", None) and self._w.value:
+            N.load().rebk_mlp_destroy(self._w)
+            self._w = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: dict):
+        arrs = [np.ascontiguousarray(params[k], dtype=np.float32) if k in params else None for k in self.NAMES]
+        for k, a in zip(self.NAMES, arrs):
+            if a is not None and a.shape != self.shapes()[k]:
+                raise ValueError(f"{k} must have shape {self.shapes()[k]}")
+        ptrs = [a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs]
+        N.check(N.load().rebk_mlp_set_params(self._w, *ptrs), "rebk_mlp_set_params")
+
+    def _get(self, fn, where):
+        out = {k: np.zeros(s, dtype=np.float32) for k, s in self.shapes().items()}
+        N.check(fn(self._w, *[out[k].ctypes.data_as(ctypes.c_void_p) for k in self.NAMES]), where)
+        return out
+
+    def params(self):
+        return self._get(N.load().rebk_mlp_get_params, "rebk_mlp_get_params")
+
+    def grads(self):
+        return self._get(N.load().rebk_mlp_get_grads, "rebk_mlp_get_grads")
+
+    def _batch(self, B):
+        if not (B.is_cuda and B.dtype == torch.float64 and B.is_contiguous() and B.dim() == 2
+                and B.shape[1] == self.in_dim):
+            raise ValueError("B must be a contiguous CUDA float64 (batch, in_dim) tensor")
+        return int(B.shape[0])
+
+    def forward(self, B: torch.Tensor, b_scale: float = 1.0, want_y: bool = False):
+        batch = self._batch(B)
+        X0 = torch.empty((batch, self.n), dtype=torch.float64, device=self.device)
+        Y = torch.empty((batch, self.m), dtype=torch.float64, device=self.device) if want_y else None
+        N.check(N.load().rebk_mlp_forward(self._w, ctypes.c_void_p(B.data_ptr()), batch, float(b_scale),
+                                          ctypes.c_void_p(X0.data_ptr()),
+                                          ctypes.c_void_p(Y.data_ptr()) if Y is not None else None),
+                "rebk_mlp_forward")
+        return (X0, Y) if want_y else X0
+
+    def grad(self, B: torch.Tensor, Xt: torch.Tensor, b_scale: float = 1.0) -> float:
+        batch = self._batch(B)
+        if not (Xt.is_cuda and Xt.dtype == torch.float64 and Xt.is_contiguous() and tuple(Xt.shape) == (batch, self.n)):
+            raise ValueError("Xt must be a contiguous CUDA float64 (batch, n) tensor")
+        loss = ctypes.c_double()
+        N.check(N.load().rebk_mlp_grad(self._w, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(Xt.data_ptr()), batch,
+                                       float(b_scale), ctypes.byref(loss)), "rebk_mlp_grad")
+        return float(loss.value)
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        N.check(N.load().rebk_mlp_adam(self._w, float(lr), float(beta1), float(beta2), float(eps)), "rebk_mlp_adam")
+
+    def train_step(self, B: torch.Tensor, Xt: torch.Tensor, lr: float, b_scale: float = 1.0) -> float:
+        batch = self._batch(B)
+        loss = ctypes.c_double()
+        N.check(N.load().rebk_mlp_train_step(self._w, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(Xt.data_ptr()),
+                                             batch, float(b_scale), float(lr), ctypes.byref(loss)),
+                "rebk_mlp_train_step")
+        return float(loss.value)
 
 
 def philox4x64_10(counter: Sequence[int], key: Sequence[int], count: int, device="cuda") -> torch.Tensor:

@@ -52,7 +52,7 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [
         ("nrhs", P), ("b_dev", P), ("x0_dev", P), ("x_ref_dev", P), ("x_out_dev", P), ("z_out_dev", P),
         ("max_iter", I64), ("tol", F64), ("check_every", I64), ("threads", I32), ("lds_budget", I32),
-        ("max_tile", I32), ("xcd_order", I32),
+        ("max_tile", I32), ("xcd_order", I32), ("z0_from_x0", I32),
     ]
 
 
@@ -79,6 +79,15 @@ SIGNATURES = {
     "rebk_batch_autotune": (ctypes.c_int, [P, ctypes.POINTER(BatchOpts), I64, ctypes.POINTER(I32),
                                            ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                            ctypes.POINTER(F64)]),
+    "rebk_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), I32, I32, P, I64, I64, I32, U64, P]),
+    "rebk_mlp_destroy": (None, [P]),
+    "rebk_mlp_set_params": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "rebk_mlp_get_params": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "rebk_mlp_forward": (ctypes.c_int, [P, P, I32, F64, P, P]),
+    "rebk_mlp_grad": (ctypes.c_int, [P, P, P, I32, F64, ctypes.POINTER(F64)]),
+    "rebk_mlp_get_grads": (ctypes.c_int, [P, P, P, P, P, P, P]),
+    "rebk_mlp_adam": (ctypes.c_int, [P, F64, F64, F64, F64]),
+    "rebk_mlp_train_step": (ctypes.c_int, [P, P, P, I32, F64, F64, ctypes.POINTER(F64)]),
     "rebk_last_error": (ctypes.c_char_p, []),
     "rebk_version": (ctypes.c_char_p, []),
 }

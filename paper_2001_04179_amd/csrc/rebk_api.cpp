@@ -766,6 +766,7 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   a.max_iter = o->max_iter;
   a.tol = o->tol;
   a.check_every = o->check_every > 0 ? o->check_every : 16;
+  a.z0_from_x0 = o->z0_from_x0 ? 1 : 0;
   int per_cu = 0;
   HIP_TRY(rebk::batch_max_blocks(b->panel_dtype, c.threads, lds_max, &per_cu));
   if (per_cu <= 0) return fail(REBK_ERR_INVALID, "batch kernel cannot run with %zu bytes of LDS and %d threads", lds_max, c.threads);
@@ -1189,3 +1190,249 @@ extern "C" int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol,
   if (steps_max) *steps_max = smax;
   return REBK_OK;
 }
+
+// ------------------------------------------------------------------ learned warm start
+
+struct rebk_mlp {
+  int32_t in = 0, hid = 0, max_batch = 0;
+  int64_t out = 0, n = 0;
+  hipStream_t stream = nullptr;
+  int64_t t = 0;  // Adam steps taken
+  bool have_grads = false;
+  // parameters W1 (hid x in), c1, W2 (hid x hid), c2, W3 (out x hid), c3: FP32 masters,
+  // gradients, Adam moments; half copies of the three weight matrices
+  float* p[6] = {};
+  float* g[6] = {};
+  float* m1[6] = {};
+  float* m2[6] = {};
+  int64_t cnt[6] = {};
+  _Float16* w16[3] = {};
+  _Float16* A16 = nullptr;  // out x n
+  // activations and signals for max_batch rows
+  _Float16 *B16 = nullptr, *H1 = nullptr, *H2 = nullptr, *Y16 = nullptr, *R16 = nullptr, *DY16 = nullptr,
+           *D2 = nullptr, *D1 = nullptr;
+  float *C = nullptr, *Y = nullptr, *X0 = nullptr, *R = nullptr, *DY = nullptr, *DH = nullptr, *pmax = nullptr;
+  double* psq = nullptr;
+  int nparts = 256;
+  std::vector<void*> owned;
+
+  ~rebk_mlp() {
+    for (void* q : owned) (void)hipFree(q);
+  }
+  template <typename T>
+  bool alloc(T*& q, size_t count) {
+    if (hipMalloc((void**)&q, (count > 0 ? count : 1) * sizeof(T)) != hipSuccess) return false;
+    owned.push_back((void*)q);
+    return true;
+  }
+};
+
+namespace {
+
+int mlp_forward_impl(rebk_mlp* w, const double* B, int32_t batch, double b_scale) {
+  hipStream_t st = w->stream;
+  const int in = w->in, hid = w->hid, out = (int)w->out, n = (int)w->n;
+  HIP_TRY(rebk::launch_to_half_f64(B, (int64_t)batch * in, b_scale, w->B16, st));
+  HIP_TRY(rebk::launch_gemm_f16(false, true, batch, hid, in, 1.f, w->B16, in, w->w16[0], in, 0.f, w->C, hid, st));
+  HIP_TRY(rebk::launch_bias_act(w->C, w->p[1], batch, hid, 1, w->H1, nullptr, st));
+  HIP_TRY(rebk::launch_gemm_f16(false, true, batch, hid, hid, 1.f, w->H1, hid, w->w16[1], hid, 0.f, w->C, hid, st));
+  HIP_TRY(rebk::launch_bias_act(w->C, w->p[3], batch, hid, 1, w->H2, nullptr, st));
+  HIP_TRY(rebk::launch_gemm_f16(false, true, batch, out, hid, 1.f, w->H2, hid, w->w16[2], hid, 0.f, w->Y, out, st));
+  HIP_TRY(rebk::launch_bias_act(w->Y, w->p[5], batch, out, 0, w->Y16, w->Y, st));
+  // x0 = A^T y for every row: X0 = Y A
+  HIP_TRY(rebk::launch_gemm_f16(false, false, batch, n, out, 1.f, w->Y16, out, w->A16, n, 0.f, w->X0, n, st));
+  return REBK_OK;
+}
+
+int mlp_check_batch(const rebk_mlp* w, int32_t batch) {
+  if (batch <= 0 || batch > w->max_batch || batch % 64)
+    return fail(REBK_ERR_INVALID, "batch must be a positive multiple of 64 up to %d", w->max_batch);
+  return REBK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rebk_mlp_create(rebk_mlp_t* out, int32_t in_dim, int32_t hidden, const double* A_dev, int64_t out_dim, int64_t n,
+                    int32_t max_batch, uint64_t seed, void* stream) {
+  g_err[0] = 0;
+  if (!out) return fail(REBK_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!A_dev) return fail(REBK_ERR_INVALID, "A is NULL");
+  if (in_dim <= 0 || hidden <= 0 || out_dim <= 0 || n <= 0 || max_batch <= 0 || in_dim % 64 || hidden % 64 ||
+      out_dim % 64 || n % 64 || max_batch % 64)
+    return fail(REBK_ERR_INVALID, "in_dim, hidden, out_dim, n and max_batch must be positive multiples of 64");
+  if (out_dim > (1 << 26) || in_dim > (1 << 26)) return fail(REBK_ERR_INVALID, "dimensions too large");
+  rebk_mlp* w = new (std::nothrow) rebk_mlp();
+  if (!w) return fail(REBK_ERR_OOM, "host allocation failed");
+  w->in = in_dim;
+  w->hid = hidden;
+  w->out = out_dim;
+  w->n = n;
+  w->max_batch = max_batch;
+  w->stream = (hipStream_t)stream;
+  const int64_t cnt[6] = {(int64_t)hidden * in_dim, hidden, (int64_t)hidden * hidden, hidden, out_dim * hidden, out_dim};
+  bool ok = true;
+  for (int q = 0; q < 6; ++q) {
+    w->cnt[q] = cnt[q];
+    ok = ok && w->alloc(w->p[q], cnt[q]) && w->alloc(w->g[q], cnt[q]) && w->alloc(w->m1[q], cnt[q]) &&
+         w->alloc(w->m2[q], cnt[q]);
+  }
+  for (int q = 0; q < 3; ++q) ok = ok && w->alloc(w->w16[q], cnt[2 * q]);
+  const int64_t B = max_batch;
+  ok = ok && w->alloc(w->A16, out_dim * n) && w->alloc(w->B16, B * in_dim) && w->alloc(w->H1, B * hidden) &&
+       w->alloc(w->H2, B * hidden) && w->alloc(w->Y16, B * out_dim) && w->alloc(w->R16, B * n) &&
+       w->alloc(w->DY16, B * out_dim) && w->alloc(w->D2, B * hidden) && w->alloc(w->D1, B * hidden) &&
+       w->alloc(w->C, B * hidden) && w->alloc(w->Y, B * out_dim) && w->alloc(w->X0, B * n) && w->alloc(w->R, B * n) &&
+       w->alloc(w->DY, B * out_dim) && w->alloc(w->DH, B * hidden) && w->alloc(w->pmax, w->nparts) &&
+       w->alloc(w->psq, w->nparts);
+  if (!ok) {
+    delete w;
+    return fail(REBK_ERR_OOM, "cannot allocate the network");
+  }
+  hipStream_t st = w->stream;
+  hipError_t e = rebk::launch_to_half_f64(A_dev, out_dim * n, 1.0, w->A16, st);
+  // weights uniform in +-1/sqrt(fan_in) (Philox, seed), biases and moments zero
+  const int fan[3] = {in_dim, hidden, hidden};
+  for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+    e = rebk::launch_init_uniform(w->p[2 * q], cnt[2 * q], (float)(1.0 / std::sqrt((double)fan[q])), seed,
+                                  (uint64_t)q, st);
+    if (e == hipSuccess) e = rebk::launch_to_half_f32(w->p[2 * q], cnt[2 * q], w->w16[q], st);
+  }
+  for (int q = 0; q < 6 && e == hipSuccess; ++q) {
+    if (q % 2 == 1) e = hipMemsetAsync(w->p[q], 0, cnt[q] * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(w->m1[q], 0, cnt[q] * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(w->m2[q], 0, cnt[q] * sizeof(float), st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete w;
+    return fail(REBK_ERR_HIP, "network setup: %s", hipGetErrorString(e));
+  }
+  *out = w;
+  return REBK_OK;
+}
+
+void rebk_mlp_destroy(rebk_mlp_t w) {
+  if (!w) return;
+  (void)hipStreamSynchronize(w->stream);
+  delete w;
+}
+
+int rebk_mlp_set_params(rebk_mlp_t w, const float* W1, const float* c1, const float* W2, const float* c2,
+                        const float* W3, const float* c3) {
+  if (!w) return fail(REBK_ERR_INVALID, "network is NULL");
+  const float* src[6] = {W1, c1, W2, c2, W3, c3};
+  for (int q = 0; q < 6; ++q) {
+    if (!src[q]) continue;
+    HIP_TRY(hipMemcpyAsync(w->p[q], src[q], w->cnt[q] * sizeof(float), hipMemcpyHostToDevice, w->stream));
+    if (q % 2 == 0) HIP_TRY(rebk::launch_to_half_f32(w->p[q], w->cnt[q], w->w16[q / 2], w->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  return REBK_OK;
+}
+
+int rebk_mlp_get_params(rebk_mlp_t w, float* W1, float* c1, float* W2, float* c2, float* W3, float* c3) {
+  if (!w) return fail(REBK_ERR_INVALID, "network is NULL");
+  float* dst[6] = {W1, c1, W2, c2, W3, c3};
+  for (int q = 0; q < 6; ++q)
+    if (dst[q]) HIP_TRY(hipMemcpyAsync(dst[q], w->p[q], w->cnt[q] * sizeof(float), hipMemcpyDeviceToHost, w->stream));
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  return REBK_OK;
+}
+
+int rebk_mlp_forward(rebk_mlp_t w, const double* B_dev, int32_t batch, double b_scale, double* X0_dev, double* Y_dev) {
+  g_err[0] = 0;
+  if (!w) return fail(REBK_ERR_INVALID, "network is NULL");
+  if (!B_dev || !X0_dev) return fail(REBK_ERR_INVALID, "B and X0 are required");
+  int rc = mlp_check_batch(w, batch);
+  if (rc != REBK_OK) return rc;
+  rc = mlp_forward_impl(w, B_dev, batch, b_scale);
+  if (rc != REBK_OK) return rc;
+  HIP_TRY(rebk::launch_widen(w->X0, (int64_t)batch * w->n, X0_dev, w->stream));
+  if (Y_dev) HIP_TRY(rebk::launch_widen(w->Y, (int64_t)batch * w->out, Y_dev, w->stream));
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  return REBK_OK;
+}
+
+int rebk_mlp_grad(rebk_mlp_t w, const double* B_dev, const double* Xt_dev, int32_t batch, double b_scale,
+                  double* loss) {
+  g_err[0] = 0;
+  if (!w) return fail(REBK_ERR_INVALID, "network is NULL");
+  if (!B_dev || !Xt_dev) return fail(REBK_ERR_INVALID, "B and Xt are required");
+  int rc = mlp_check_batch(w, batch);
+  if (rc != REBK_OK) return rc;
+  rc = mlp_forward_impl(w, B_dev, batch, b_scale);
+  if (rc != REBK_OK) return rc;
+  hipStream_t st = w->stream;
+  const int in = w->in, hid = w->hid, out = (int)w->out, n = (int)w->n;
+  const int64_t rn = (int64_t)batch * n;
+  HIP_TRY(rebk::launch_mlp_residual(w->X0, Xt_dev, rn, w->R, w->psq, w->pmax, w->nparts, st));
+  std::vector<double> sq(w->nparts);
+  std::vector<float> mx(w->nparts);
+  HIP_TRY(hipMemcpyAsync(sq.data(), w->psq, w->nparts * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(mx.data(), w->pmax, w->nparts * sizeof(float), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double total = 0.0, rmax = 0.0;
+  for (int q = 0; q < w->nparts; ++q) {
+    total += sq[q];
+    rmax = mx[q] > rmax ? mx[q] : rmax;
+  }
+  if (loss) *loss = total / (2.0 * batch);
+  if (!std::isfinite(total)) return fail(REBK_ERR_INVALID, "the loss is not finite");
+  // residual scaled by a power of two (largest magnitude in [4, 8]) before half rounding
+  const double s = rmax > 0.0 ? std::ldexp(1.0, 3 - (int)std::ceil(std::log2(rmax))) : 1.0;
+  const float k = (float)(1.0 / (s * batch));
+  HIP_TRY(rebk::launch_scale_half(w->R, rn, (float)s, w->R16, st));
+  // dY = (s R) A^T
+  HIP_TRY(rebk::launch_gemm_f16(false, true, batch, out, n, 1.f, w->R16, n, w->A16, n, 0.f, w->DY, out, st));
+  HIP_TRY(rebk::launch_to_half_f32(w->DY, (int64_t)batch * out, w->DY16, st));
+  // layer 3
+  HIP_TRY(rebk::launch_gemm_f16(true, false, out, hid, batch, k, w->DY16, out, w->H2, hid, 0.f, w->g[4], hid, st));
+  HIP_TRY(rebk::launch_colsum_half(w->DY16, batch, out, k, w->g[5], st));
+  HIP_TRY(rebk::launch_gemm_f16(false, false, batch, hid, out, 1.f, w->DY16, out, w->w16[2], hid, 0.f, w->DH, hid, st));
+  HIP_TRY(rebk::launch_relu_back(w->DH, w->H2, (int64_t)batch * hid, w->D2, st));
+  // layer 2
+  HIP_TRY(rebk::launch_gemm_f16(true, false, hid, hid, batch, k, w->D2, hid, w->H1, hid, 0.f, w->g[2], hid, st));
+  HIP_TRY(rebk::launch_colsum_half(w->D2, batch, hid, k, w->g[3], st));
+  HIP_TRY(rebk::launch_gemm_f16(false, false, batch, hid, hid, 1.f, w->D2, hid, w->w16[1], hid, 0.f, w->DH, hid, st));
+  HIP_TRY(rebk::launch_relu_back(w->DH, w->H1, (int64_t)batch * hid, w->D1, st));
+  // layer 1
+  HIP_TRY(rebk::launch_gemm_f16(true, false, hid, in, batch, k, w->D1, hid, w->B16, in, 0.f, w->g[0], in, st));
+  HIP_TRY(rebk::launch_colsum_half(w->D1, batch, hid, k, w->g[1], st));
+  w->have_grads = true;
+  return REBK_OK;
+}
+
+int rebk_mlp_get_grads(rebk_mlp_t w, float* gW1, float* gc1, float* gW2, float* gc2, float* gW3, float* gc3) {
+  if (!w) return fail(REBK_ERR_INVALID, "network is NULL");
+  if (!w->have_grads) return fail(REBK_ERR_INVALID, "no gradients computed yet");
+  float* dst[6] = {gW1, gc1, gW2, gc2, gW3, gc3};
+  for (int q = 0; q < 6; ++q)
+    if (dst[q]) HIP_TRY(hipMemcpyAsync(dst[q], w->g[q], w->cnt[q] * sizeof(float), hipMemcpyDeviceToHost, w->stream));
+  HIP_TRY(hipStreamSynchronize(w->stream));
+  return REBK_OK;
+}
+
+int rebk_mlp_adam(rebk_mlp_t w, double lr, double beta1, double beta2, double eps) {
+  if (!w) return fail(REBK_ERR_INVALID, "network is NULL");
+  if (!w->have_grads) return fail(REBK_ERR_INVALID, "no gradients computed yet");
+  if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+    return fail(REBK_ERR_INVALID, "bad Adam hyper-parameters");
+  w->t += 1;
+  const float c1 = (float)(1.0 - std::pow(beta1, (double)w->t)), c2 = (float)(1.0 - std::pow(beta2, (double)w->t));
+  for (int q = 0; q < 6; ++q)
+    HIP_TRY(rebk::launch_adam(w->p[q], w->g[q], w->m1[q], w->m2[q], w->cnt[q], (float)lr, (float)beta1, (float)beta2,
+                              (float)eps, c1, c2, q % 2 == 0 ? w->w16[q / 2] : nullptr, w->stream));
+  return REBK_OK;
+}
+
+int rebk_mlp_train_step(rebk_mlp_t w, const double* B_dev, const double* Xt_dev, int32_t batch, double b_scale,
+                        double lr, double* loss) {
+  int rc = rebk_mlp_grad(w, B_dev, Xt_dev, batch, b_scale, loss);
+  if (rc != REBK_OK) return rc;
+  return rebk_mlp_adam(w, lr, 0.9, 0.999, 1e-8);
+}
+
+}  // extern "C"

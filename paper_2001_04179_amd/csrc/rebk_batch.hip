@@ -165,6 +165,31 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     for (int64_t e = tid; e < (int64_t)R * n; e += T) x[e] = 0.0;
   }
 
+  if (a.z0_from_x0 && tk.x_in) {
+    // z0 = b - A x0 (a start in b + range(A), as Theorem 7 asks), one thread per row, from the
+    // row panels: row l of block i at n * r0_i + c * nI_i + (l - r0_i)
+    __syncthreads();
+    for (int64_t l = tid; l < m; l += T) {
+      int lo = 0, hi = S.s - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_off[mid] <= l) lo = mid; else hi = mid - 1;
+      }
+      const int64_t rb = row_off[lo], nb = row_off[lo + 1] - rb;
+      const GLOBAL_AS TP* p = Arow + n * rb + (l - rb);
+      double acc[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) acc[k] = 0.0;
+      for (int64_t c = 0; c < n; ++c) {
+        const double av = widen(p[c * nb]);
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[k] += av * x[k * n + c];
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) z[k * m + l] = bvec[k * m + l] - acc[k];
+    }
+    __syncthreads();
+  }
   const bool checking = tk.x_ref != nullptr;
   const bool stopping = checking && a.tol > 0.0;
   const int64_t ce = a.check_every > 0 ? a.check_every : 1;

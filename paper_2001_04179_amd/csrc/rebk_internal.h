@@ -101,6 +101,7 @@ struct BatchArgs {
   int64_t max_iter;
   double tol;                // relative tolerance per right-hand side (<= 0: none)
   int64_t check_every;
+  int32_t z0_from_x0;        // with x_in: start from z0 = b - A x0 (else z0 = b)
 };
 
 // Launchers (defined in rebk_kernels.hip).  All return hipError_t.
@@ -149,6 +150,23 @@ hipError_t launch_gram(const void* P, int panel_dtype, const GramDesc* desc, int
                        const int32_t* tile_a1, const int32_t* tile_a2, double* gram, hipStream_t st);
 hipError_t launch_power(const GramDesc* desc, int nblocks, int max_d, const double* gram, int max_steps, double rtol,
                         double* lam, double* trace, int32_t* steps, hipStream_t st);
+
+// warm-start network kernels (half-precision operands, FP32 accumulation)
+hipError_t launch_gemm_f16(bool ta, bool tb, int M, int N, int K, float alpha, const _Float16* A, int lda,
+                           const _Float16* B, int ldb, float beta, float* C, int ldc, hipStream_t st);
+hipError_t launch_to_half_f64(const double* in, int64_t count, double scale, _Float16* out, hipStream_t st);
+hipError_t launch_to_half_f32(const float* in, int64_t count, _Float16* out, hipStream_t st);
+hipError_t launch_bias_act(const float* C, const float* bias, int64_t rows, int cols, int relu, _Float16* out16,
+                           float* out32, hipStream_t st);
+hipError_t launch_mlp_residual(const float* X0, const double* Xt, int64_t count, float* R, double* part_sq,
+                               float* part_max, int nparts, hipStream_t st);
+hipError_t launch_scale_half(const float* in, int64_t count, float s, _Float16* out, hipStream_t st);
+hipError_t launch_relu_back(const float* D, const _Float16* H, int64_t count, _Float16* out, hipStream_t st);
+hipError_t launch_colsum_half(const _Float16* D, int rows, int cols, float scale, float* out, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
+                       float eps, float c1, float c2, _Float16* p16, hipStream_t st);
+hipError_t launch_init_uniform(float* p, int64_t count, float bound, uint64_t seed, uint64_t tag, hipStream_t st);
+hipError_t launch_widen(const float* in, int64_t count, double* out, hipStream_t st);
 
 // refinement kernels (FP64, caller's row-major A with leading dimension lda)
 int64_t refine_chunks(int64_t m);  // row chunks of the transposed product (partial: chunks x n doubles)

@@ -1,0 +1,128 @@
+"""Learned warm start: the network's GPU kernels against the FP64 oracle, training, and REBK from
+the network's start point against the oracle.
+
+Forward and gradients are compared with the oracle evaluated with half-precision rounding at the
+points where the GPU stores half precision; the GPU accumulates in FP32, so a value that lands
+next to a half-precision rounding boundary may round the other way: the bar is a few half-precision
+units (2^-11) in norm.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+from paper_2001_04179_amd import workloads as W
+
+from _helpers import RTOL_F64, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+HALF_ULP = 2.0 ** -11
+
+
+def setup(rebk, in_dim=128, hidden=64, m=128, n=64, batch=64, seed=0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    params = M.init_params(in_dim, hidden, m, rng)
+    for k in ("c1", "c2", "c3"):
+        params[k] = 0.05 * rng.standard_normal(params[k].shape)
+    params = {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}  # FP32-exact values
+    B = rng.standard_normal((batch, in_dim))
+    Xt = rng.standard_normal((batch, n))
+    net = rebk.WarmStart(to_dev(A), in_dim, hidden, max_batch=batch)
+    net.set_params(params)
+    return net, A, params, B, Xt
+
+
+def test_forward_matches_oracle(rebk):
+    net, A, params, B, Xt = setup(rebk)
+    X0, Y = net.forward(to_dev(B), want_y=True)
+    ref = M.forward(params, B, A, round16=True)
+    assert rel(Y.cpu().numpy(), ref["y"]) < 4 * HALF_ULP
+    assert rel(X0.cpu().numpy(), ref["x0"]) < 4 * HALF_ULP
+    net.close()
+
+
+def test_gradients_match_oracle(rebk):
+    net, A, params, B, Xt = setup(rebk, seed=1)
+    loss = net.grad(to_dev(B), to_dev(Xt))
+    g = net.grads()
+    ref_loss, ref = M.loss_and_grads(params, B, A, Xt, round16=True)
+    assert abs(loss - ref_loss) < 8 * HALF_ULP * ref_loss
+    for k in M.PARAMS:
+        assert rel(g[k], ref[k]) < 8 * HALF_ULP, (k, rel(g[k], ref[k]))
+    # and within the half-precision level of the exact FP64 gradients
+    _, exact = M.loss_and_grads(params, B, A, Xt)
+    for k in M.PARAMS:
+        assert rel(g[k], exact[k]) < 3e-2, k
+    net.close()
+
+
+def test_adam_step_matches_oracle(rebk):
+    net, A, params, B, Xt = setup(rebk, seed=2)
+    net.grad(to_dev(B), to_dev(Xt))
+    g = {k: v.astype(np.float64) for k, v in net.grads().items()}
+    lr = 1e-3
+    net.adam(lr)
+    got = net.params()
+    want = M.adam_step(params, g, {}, lr)
+    for k in M.PARAMS:
+        assert rel(got[k], want[k]) < 1e-6, k
+    net.close()
+
+
+def test_training_reduces_the_loss(rebk):
+    """The targets are a linear function of the inputs (x = P b for a fixed P); 300 Adam steps."""
+    rng = np.random.default_rng(3)
+    in_dim, hidden, m, n, batch = 128, 128, 128, 64, 128
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    P = rng.standard_normal((n, in_dim)) / np.sqrt(in_dim)
+    B = rng.standard_normal((batch, in_dim))
+    Xt = B @ P.T
+    net = rebk.WarmStart(to_dev(A), in_dim, hidden, max_batch=batch, seed=5)
+    Bd, Xd = to_dev(B), to_dev(Xt)
+    first = net.train_step(Bd, Xd, lr=3e-3)
+    for _ in range(300):
+        last = net.train_step(Bd, Xd, lr=3e-3)
+    assert last < 0.1 * first, (first, last)
+    net.close()
+
+
+def test_warm_started_solve_matches_oracle(rebk, oracle_lib):
+    """REBK from x0 = A^T y (network) and z0 = b - A x0 (batched kernel) equals the oracle run from
+    the same start, and reaches the tolerance."""
+    rng = np.random.default_rng(4)
+    m, n, batch = 256, 64, 64
+    S = W.type2(m, n, rng_seed=9, noise=0.05, row_tau=32, col_tau=8)
+    Bmat = np.stack([S.A @ rng.standard_normal(n) + 0.0 for _ in range(batch)])
+    net = rebk.WarmStart(to_dev(S.A), m, 64, max_batch=batch, seed=1)
+    X0 = net.forward(to_dev(Bmat))
+    x0 = X0.cpu().numpy()
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, 0)
+    batch_solver = rebk.Batch([solver], sys_ids=[0])
+    K = 80
+    out = batch_solver.solve([to_dev(Bmat)], x0=[X0.contiguous()], max_iter=K, z0_from_x0=True, want_z=True)
+    X = out["x"][0].cpu().numpy()
+    for k in range(8):
+        z0 = Bmat[k] - S.A @ x0[k]
+        ref = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, 0, Bmat[k], x0=x0[k], z0=z0, max_iter=K,
+                                    trace=False)
+        assert rel(X[k], ref["x"]) <= RTOL_F64
+    # x0 lies in range(A^T)
+    _, sv, Vt = np.linalg.svd(S.A, full_matrices=False)
+    assert np.linalg.norm(x0 - (x0 @ Vt.T) @ Vt) < 1e-10 * np.linalg.norm(x0)
+    batch_solver.close()
+    solver.close()
+    net.close()
+
+
+def test_invalid(rebk):
+    rng = np.random.default_rng(0)
+    A = to_dev(rng.standard_normal((128, 64)))
+    with pytest.raises(rebk.RebkError):
+        rebk.WarmStart(A, 100, 64)          # not a multiple of 64
+    net = rebk.WarmStart(A, 128, 64, max_batch=128)
+    with pytest.raises(rebk.RebkError):
+        net.forward(to_dev(rng.standard_normal((32, 128))))   # batch not a multiple of 64
+    with pytest.raises(rebk.RebkError):
+        net.adam(1e-3)                       # no gradients yet
+    net.close()
