@@ -52,9 +52,16 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-iters", type=int, default=2000)
     p.add_argument("--scale", type=int, default=1, help="divide the problem dimensions (quick checks only)")
-    p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched", "mixed", "sweeps"],
+    p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched", "mixed", "sweeps", "warmstart"],
                    help="rank1500: the 20000 x 2000 single system; batched: 256 systems x 16 right-hand sides; "
                         "mixed: the 2000 x 50000 rank-1200 system, BF16/FP16 panels with FP64 refinement")
+    p.add_argument("--ws-train", type=int, default=16384,
+                   help="training right-hand sides (65536 in the full configuration; REBK makes their targets)")
+    p.add_argument("--ws-eval", type=int, default=2048)
+    p.add_argument("--ws-epochs", type=int, default=60)
+    p.add_argument("--ws-gen-iters", type=int, default=0,
+                   help="iterations REBK runs to produce the training targets (0: the count that takes the "
+                        "held-out right-hand sides to relative error 1e-3)")
     p.add_argument("--sweep-scale", type=int, default=4,
                    help="divide the block-size sweep's 20000 x 5000 systems by this factor")
     p.add_argument("--mixed-inner", default="500,1000,2000,4000",
@@ -462,6 +469,120 @@ def bench_sweeps(args):
     print(json.dumps({"sweeps": out, "stop_rule": "||x - A^+ b|| <= 1e-5 (absolute)", "scale_figure2": sc}))
 
 
+def bench_warmstart(args):
+    """Learned warm start on the 8192 x 1024 rank-768 system: train the network on REBK-generated
+    (b, x) pairs, then time REBK to relative error 1e-6 on held-out right-hand sides from
+    x0 = 0, z0 = b (plain) and from the network's x0 = A^T y, z0 = b - A x0 (warm)."""
+    import torch
+    import paper_2001_04179_amd as rebk
+    from paper_2001_04179_amd import workloads as W
+    t0 = time.perf_counter()
+    P = W.warmstart_problem(n_train=args.ws_train, n_eval=args.ws_eval)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    A_d, ro, co, alpha = P["A_dev"], P["row_off"], P["col_off"], P["alpha"]
+    m, n = A_d.shape
+    print(f"# generated in {t_gen:.1f} s, alpha {alpha:.3f}", file=sys.stderr, flush=True)
+    solver = rebk.Solver(A_d, ro, co, alpha, 0, panel_dtype="f32")
+    batch = rebk.Batch([solver], sys_ids=[0])
+    tol = args.tol
+    Bev, Xev = P["B_eval"], P["X_eval_ref"]
+
+    cap = [2_000_000]
+
+    def solve_eval(x0=None):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o = batch.solve([Bev], x_ref=[Xev], x0=None if x0 is None else [x0], max_iter=cap[0], tol=tol,
+                        check_every=16, z0_from_x0=x0 is not None)
+        torch.cuda.synchronize()
+        return o, time.perf_counter() - t1
+
+    cold, t_cold = solve_eval()
+    print(f"# cold: {t_cold:.2f} s, iterations mean {cold['iterations'].mean():.0f} max {cold['iterations'].max()}",
+          file=sys.stderr, flush=True)
+    cap[0] = int(2 * cold["iterations"].max())  # a warm start that does not converge stops here
+    # training targets: REBK on the training right-hand sides for the iteration count that brings the
+    # held-out right-hand sides to relative error 1e-3 (the network resolves less than that)
+    if args.ws_gen_iters:
+        K_gen = args.ws_gen_iters
+    else:
+        probe = batch.solve([Bev], x_ref=[Xev], max_iter=2_000_000, tol=1e-3, check_every=16)
+        K_gen = int(probe["iterations"].max())
+    Btr = P["B_train"]
+    t1 = time.perf_counter()
+    Xtr = torch.empty_like(P["X_train_ref"])
+    step = 4096
+    for c0 in range(0, Btr.shape[0], step):
+        g = batch.solve([Btr[c0:c0 + step].contiguous()], max_iter=K_gen)
+        Xtr[c0:c0 + step] = g["x"][0]
+        print(f"# targets {c0 + step} / {Btr.shape[0]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t1
+    target_err = float(((Xtr - P["X_train_ref"]).norm(dim=1) / P["X_train_ref"].norm(dim=1)).max())
+    print(f"# targets: {K_gen} iterations on {Btr.shape[0]} right-hand sides in {t_targets:.1f} s, "
+          f"max rel err vs A^+ b {target_err:.2e}", file=sys.stderr, flush=True)
+    # training
+    bs = 256
+    b_scale = 1.0 / float(Btr.pow(2).mean().sqrt())
+    net = rebk.WarmStart(A_d, m, 512, max_batch=bs, seed=7)
+    nb = Btr.shape[0] // bs
+    gen_perm = torch.Generator(device="cpu").manual_seed(11)
+    losses = []
+    t1 = time.perf_counter()
+    for ep in range(args.ws_epochs):
+        perm = torch.randperm(nb * bs, generator=gen_perm).to(A_d.device)
+        lr = 1e-3 if ep < int(0.8 * args.ws_epochs) else 2e-4
+        ep_loss = 0.0
+        for q in range(nb):
+            idx = perm[q * bs:(q + 1) * bs]
+            ep_loss += net.train_step(Btr[idx].contiguous(), Xtr[idx].contiguous(), lr=lr, b_scale=b_scale)
+        losses.append(ep_loss / nb)
+        if ep % 5 == 0 or ep == args.ws_epochs - 1:
+            print(f"# epoch {ep}: loss {losses[-1]:.4e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    # warm start on the held-out set
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X0 = torch.cat([net.forward(Bev[q:q + bs].contiguous(), b_scale=b_scale) for q in range(0, Bev.shape[0], bs)])
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t1
+    warm, t_warm = solve_eval(X0)
+    x0_err = ((X0 - Xev).norm(dim=1) / Xev.norm(dim=1)).cpu().numpy()
+    resid0 = ((Bev - X0 @ A_d.T).norm(dim=1) / Bev.norm(dim=1)).cpu().numpy()  # report only
+    print(f"# warm: {t_warm:.2f} s (+{t_infer:.3f} s inference), iterations mean {warm['iterations'].mean():.0f}",
+          file=sys.stderr, flush=True)
+    N = Bev.shape[0]
+    total_warm = t_warm + t_infer
+    line = {
+        "metric": "time & iters to rel err 1e-6 (solves/s, GB/s vs roofline), chosen form vs plain REBK",
+        "value": N / total_warm, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": total_warm * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"learned warm start: A = U V ({m} x {n}, rank {P['rank']}), {Btr.shape[0]} training / "
+                               f"{N} held-out right-hand sides, network {m}-512-512-{m}, tol {tol:g}",
+                   "panel_dtype": "f32", "epochs": args.ws_epochs, "batch": bs},
+        "warm": {"seconds": t_warm, "inference_seconds": t_infer, "iterations_mean": float(warm["iterations"].mean()),
+                 "iterations_median": float(np.median(warm["iterations"])), "status": warm["status"],
+                 "rel_err_max": float(warm["rel_err"].max())},
+        "plain": {"seconds": t_cold, "iterations_mean": float(cold["iterations"].mean()),
+                  "iterations_median": float(np.median(cold["iterations"])), "status": cold["status"],
+                  "rel_err_max": float(cold["rel_err"].max()), "solves_per_s": N / t_cold},
+        "speedup_vs_plain": t_cold / total_warm,
+        "x0_rel_err": {"median": float(np.median(x0_err)), "max": float(np.max(x0_err))},
+        "fallback_count": int(np.sum(resid0 >= 1.0)),
+        "training": {"seconds": t_train, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
+                     "targets": f"REBK, {K_gen} iterations per right-hand side", "target_rel_err_max": target_err,
+                     "target_seconds": t_targets},
+        "prep_seconds": {"generate": t_gen},
+    }
+    print(json.dumps(line))
+    net.close()
+    batch.close()
+    solver.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -478,6 +599,9 @@ def main():
         return
     if args.workload == "sweeps":
         bench_sweeps(args)
+        return
+    if args.workload == "warmstart":
+        bench_warmstart(args)
         return
     import torch
     import paper_2001_04179_amd as rebk

@@ -264,7 +264,7 @@ void rebk_batch_destroy(rebk_batch_t b);
 
 /* Options of rebk_batch_solve and rebk_batch_autotune.  Zero-initialise. */
 typedef struct {
-    const int32_t *nrhs;            /* host, nsys entries: right-hand sides of system s (1..4096) */
+    const int32_t *nrhs;            /* host, nsys entries: right-hand sides of system s (1..2^20) */
     const double *const *b_dev;     /* host array of nsys device pointers: nrhs[s] right-hand
                                        sides of m_s entries each, one after another (required) */
     const double *const *x0_dev;    /* NULL, or host array of nsys device pointers (entries may be
@@ -287,7 +287,8 @@ typedef struct {
     int32_t xcd_order;              /* 1: dispatch the tasks of a system to one XCD (shared L2);
                                        0: plain longest-first order; -1: tuned (default 1) */
     int32_t z0_from_x0;             /* 1: where x0 is given, start from z0 = b - A x0 (computed from
-                                       the stored panels) instead of z0 = b */
+                                       the stored panels) instead of z0 = b; a right-hand side
+                                       whose ||b - A x0|| >= ||b|| falls back to x0 = 0, z0 = b */
 } rebk_batch_opts_t;
 
 /* Result of one right-hand side of a batch. */
@@ -347,9 +348,10 @@ int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol, double *be
  * hypotheses of Theorem 7, so REBK from (x0, z0) still converges to A^+ b
  * (plain REBK from x0 = 0, z0 = b is the fallback and the judge of its
  * error).  The network is
- *   h1 = relu(W1 (s b) + c1),  h2 = relu(W2 h1 + c2),  y = W3 h2 + c3
+ *   h1 = relu(W1 (s b) + c1),  h2 = relu(W2 h1 + c2),  y = W3 h2 + c3,
+ *   x0 = out_scale A^T y
  * (s: a scale of the input), trained with Adam (Kingma and Ba) on
- *   loss = 1 / (2 batch) * sum over the batch ||A^T y - x_target||^2.
+ *   loss = 1 / (2 batch) * sum over the batch ||x0 - x_target||^2.
  * Every product runs on the matrix cores with half-precision operands and
  * FP32 accumulation; the weights have FP32 masters.  Batches are row-major
  * (one right-hand side per row), batch a multiple of 64 up to max_batch.
@@ -359,12 +361,14 @@ typedef struct rebk_mlp *rebk_mlp_t;
 /*
  * Create a network in_dim -> hidden -> hidden -> out_dim for the matrix A
  * (A_dev: out_dim x n, FP64 row-major, copied in half precision; out_dim is
- * m).  All sizes must be positive multiples of 64.  Weights start uniform in
- * +-1/sqrt(fan_in) from Philox4x64-10 with the given seed, biases at zero.
- * Errors: REBK_ERR_INVALID, REBK_ERR_OOM, REBK_ERR_HIP.
+ * m), with x0 = out_scale A^T y (out_scale > 0, e.g. 1/sqrt(m) so that y is
+ * of order one).  All sizes must be positive multiples of 64.  Weights start
+ * uniform in +-1/sqrt(fan_in) from Philox4x64-10 with the given seed, biases
+ * at zero.  Errors: REBK_ERR_INVALID, REBK_ERR_OOM, REBK_ERR_HIP.
  */
 int rebk_mlp_create(rebk_mlp_t *out, int32_t in_dim, int32_t hidden, const double *A_dev,
-                    int64_t out_dim, int64_t n, int32_t max_batch, uint64_t seed, void *stream);
+                    int64_t out_dim, int64_t n, double out_scale, int32_t max_batch, uint64_t seed,
+                    void *stream);
 void rebk_mlp_destroy(rebk_mlp_t w);
 
 /* Copy parameters from / to host FP32 arrays (W1 hidden x in_dim, c1 hidden, W2 hidden x hidden,
@@ -374,8 +378,10 @@ int rebk_mlp_set_params(rebk_mlp_t w, const float *W1, const float *c1, const fl
 int rebk_mlp_get_params(rebk_mlp_t w, float *W1, float *c1, float *W2, float *c2, float *W3,
                         float *c3);
 
-/* Inference: X0_dev (batch x n, FP64) = rows of A^T y for the rows of B_dev (batch x in_dim,
- * FP64, scaled by b_scale); Y_dev (batch x out_dim, FP64) receives y if not NULL. */
+/* Inference: X0_dev (batch x n, FP64) = rows of out_scale A^T y for the rows of B_dev (batch x
+ * in_dim, FP64, scaled by b_scale), formed in FP64 from the FP64 A so that x0 lies in range(A^T)
+ * to FP64 rounding (training uses the half-precision product); Y_dev (batch x out_dim, FP64)
+ * receives y if not NULL. */
 int rebk_mlp_forward(rebk_mlp_t w, const double *B_dev, int32_t batch, double b_scale,
                      double *X0_dev, double *Y_dev);
 

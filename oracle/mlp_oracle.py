@@ -8,8 +8,9 @@ x0 = A^T y in range(A^T) -- the hypothesis of Theorem 7 -- with y produced from 
 network, and z0 = b - A x0 (in b + range(A), the other hypothesis).  The network and its
 training objective are defined here in plain numpy:
 
-  h1 = relu(W1 b + c1),  h2 = relu(W2 h1 + c2),  y = W3 h2 + c3,  x0 = A^T y
+  h1 = relu(W1 b + c1),  h2 = relu(W2 h1 + c2),  y = W3 h2 + c3,  x0 = out_scale A^T y
   loss = 1 / (2 batch) * sum over the batch of ||x0 - x_target||^2
+(out_scale a fixed constant, 1/sqrt(m) by default, so that y is of order one)
 
 with the backward pass of that composition and the Adam update (Kingma and Ba, ICLR 2015):
   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
@@ -46,8 +47,8 @@ def residual_scale(R, target_log2=3):
     return float(2.0 ** (target_log2 - e))
 
 
-def forward(params, B, A, round16=False):
-    """Activations of the network for the batch B (rows) and x0 = A^T y (rows of Y A)."""
+def forward(params, B, A, round16=False, out_scale=1.0):
+    """Activations of the network for the batch B (rows) and x0 = out_scale A^T y (rows of Y A)."""
     r = to_half if round16 else (lambda v: np.asarray(v, dtype=np.float64))
     W1, c1, W2, c2, W3, c3 = (np.asarray(params[k], dtype=np.float64) for k in PARAMS)
     Bq = r(B)
@@ -55,21 +56,21 @@ def forward(params, B, A, round16=False):
     h2 = r(np.maximum(h1 @ r(W2).T + c2, 0.0))
     y = h2 @ r(W3).T + c3
     yq = r(y)
-    x0 = yq @ r(A)
+    x0 = out_scale * (yq @ r(A))
     return {"B": Bq, "h1": h1, "h2": h2, "y": y, "yq": yq, "x0": x0}
 
 
-def loss_and_grads(params, B, A, Xt, round16=False):
+def loss_and_grads(params, B, A, Xt, round16=False, out_scale=1.0):
     """Loss and gradients of every parameter (FP64; see the module header for round16)."""
     r = to_half if round16 else (lambda v: np.asarray(v, dtype=np.float64))
     W1, c1, W2, c2, W3, c3 = (np.asarray(params[k], dtype=np.float64) for k in PARAMS)
-    f = forward(params, B, A, round16)
+    f = forward(params, B, A, round16, out_scale)
     batch = B.shape[0]
     R = f["x0"] - Xt
     loss = float(np.sum(R * R)) / (2.0 * batch)
     s = residual_scale(R) if round16 else 1.0
     Aq = r(A)
-    dY = r((r(s * R)) @ Aq.T)                       # s * dL/dy * batch
+    dY = r((r(s * R)) @ Aq.T)                       # s * dL/dy * batch / out_scale
     gW3 = dY.T @ f["h2"]
     gc3 = dY.sum(axis=0)
     dH2 = r((dY @ r(W3)) * (f["h2"] > 0))
@@ -78,7 +79,7 @@ def loss_and_grads(params, B, A, Xt, round16=False):
     dH1 = r((dH2 @ r(W2)) * (f["h1"] > 0))
     gW1 = dH1.T @ f["B"]
     gc1 = dH1.sum(axis=0)
-    k = 1.0 / (s * batch)
+    k = out_scale / (s * batch)
     grads = {"W1": gW1 * k, "c1": gc1 * k, "W2": gW2 * k, "c2": gc2 * k, "W3": gW3 * k, "c3": gc3 * k}
     return loss, grads
 

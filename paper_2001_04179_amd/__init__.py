@@ -355,19 +355,23 @@ class Batch:
 
 class WarmStart:
     """``rebk_mlp_*``: the learned warm start network in_dim -> hidden -> hidden -> m for A (m x n,
-    CUDA float64).  forward(B) gives rows x0 = A^T y; grad / adam / train_step train it."""
+    CUDA float64).  forward(B) gives rows x0 = out_scale A^T y (out_scale defaults to 1/sqrt(m));
+    grad / adam / train_step train it."""
 
     NAMES = ("W1", "c1", "W2", "c2", "W3", "c3")
 
-    def __init__(self, A: torch.Tensor, in_dim: int, hidden: int = 512, max_batch: int = 256, seed: int = 0):
+    def __init__(self, A: torch.Tensor, in_dim: int, hidden: int = 512, max_batch: int = 256, seed: int = 0,
+                 out_scale: Optional[float] = None):
         if not (A.is_cuda and A.dtype == torch.float64 and A.dim() == 2 and A.is_contiguous()):
             raise ValueError("A must be a contiguous CUDA float64 matrix")
         self.m, self.n = int(A.shape[0]), int(A.shape[1])
         self.in_dim, self.hidden, self.max_batch = int(in_dim), int(hidden), int(max_batch)
         self.device = A.device
+        self.out_scale = float(out_scale) if out_scale is not None else 1.0 / np.sqrt(self.m)
         w = ctypes.c_void_p()
         N.check(N.load().rebk_mlp_create(ctypes.byref(w), self.in_dim, self.hidden, ctypes.c_void_p(A.data_ptr()),
-                                         self.m, self.n, self.max_batch, ctypes.c_uint64(int(seed)), _stream_ptr()),
+                                         self.m, self.n, self.out_scale, self.max_batch, ctypes.c_uint64(int(seed)),
+                                         _stream_ptr()),
                 "rebk_mlp_create")
         self._w = w
 

@@ -79,7 +79,7 @@ SIGNATURES = {
     "rebk_batch_autotune": (ctypes.c_int, [P, ctypes.POINTER(BatchOpts), I64, ctypes.POINTER(I32),
                                            ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                            ctypes.POINTER(F64)]),
-    "rebk_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), I32, I32, P, I64, I64, I32, U64, P]),
+    "rebk_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), I32, I32, P, I64, I64, F64, I32, U64, P]),
     "rebk_mlp_destroy": (None, [P]),
     "rebk_mlp_set_params": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "rebk_mlp_get_params": (ctypes.c_int, [P, P, P, P, P, P, P]),

@@ -695,28 +695,41 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
       done += R;
     }
   }
-  // order: longest first; with xcd_order, whole systems go to the least loaded of the 8 XCDs and
-  // workgroup 8*slot + x runs slot `slot` of XCD x
+  // order: longest first; with xcd_order, the tiles of a system are cut into groups of at most
+  // one XCD's worth of compute units (so a system with many right-hand sides still spreads over
+  // the chip), groups go to the least loaded of the 8 XCDs, and workgroup 8*slot + x runs slot
+  // `slot` of XCD x
   std::vector<int32_t> order;  // tile index per workgroup, -1 for an empty slot
   {
     std::vector<int32_t> idx(tiles.size());
     for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int32_t)q;
     if (c.xcd_order) {
-      std::vector<double> sys_cost(ns, 0.0);
-      for (const Tile& t : tiles) sys_cost[t.sys] += t.cost;
-      std::vector<int32_t> sys_idx(ns);
-      for (int32_t s = 0; s < ns; ++s) sys_idx[s] = s;
-      std::stable_sort(sys_idx.begin(), sys_idx.end(), [&](int32_t p, int32_t q) { return sys_cost[p] > sys_cost[q]; });
-      std::vector<std::vector<int32_t>> lists(8);
-      std::vector<double> load(8, 0.0);
+      const size_t per_xcd = (size_t)(b->cus >= 8 ? b->cus / 8 : 1);
       std::vector<std::vector<int32_t>> by_sys(ns);
       for (size_t q = 0; q < tiles.size(); ++q) by_sys[tiles[q].sys].push_back((int32_t)q);
-      for (int32_t s : sys_idx) {
+      std::vector<std::vector<int32_t>> groups;
+      std::vector<double> gcost;
+      for (int32_t s = 0; s < ns; ++s)
+        for (size_t q0 = 0; q0 < by_sys[s].size(); q0 += per_xcd) {
+          groups.emplace_back();
+          double cst = 0.0;
+          for (size_t q = q0; q < by_sys[s].size() && q < q0 + per_xcd; ++q) {
+            groups.back().push_back(by_sys[s][q]);
+            cst += tiles[by_sys[s][q]].cost;
+          }
+          gcost.push_back(cst);
+        }
+      std::vector<int32_t> gidx(groups.size());
+      for (size_t g = 0; g < gidx.size(); ++g) gidx[g] = (int32_t)g;
+      std::stable_sort(gidx.begin(), gidx.end(), [&](int32_t p, int32_t q) { return gcost[p] > gcost[q]; });
+      std::vector<std::vector<int32_t>> lists(8);
+      std::vector<double> load(8, 0.0);
+      for (int32_t g : gidx) {
         int best = 0;
         for (int x = 1; x < 8; ++x)
           if (load[x] < load[best]) best = x;
-        for (int32_t q : by_sys[s]) lists[best].push_back(q);
-        load[best] += sys_cost[s];
+        for (int32_t q : groups[g]) lists[best].push_back(q);
+        load[best] += gcost[g];
       }
       size_t slots = 0;
       for (auto& l : lists) slots = l.size() > slots ? l.size() : slots;
@@ -819,7 +832,7 @@ int check_batch_opts(const rebk_batch* b, const rebk_batch_opts_t* o) {
   if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
   if (o->tol > 0.0 && !o->x_ref_dev) return fail(REBK_ERR_INVALID, "a tolerance needs x_ref");
   for (int32_t s = 0; s < b->nsys; ++s) {
-    if (o->nrhs[s] < 1 || o->nrhs[s] > 4096) return fail(REBK_ERR_INVALID, "nrhs[%d] must be in 1..4096", s);
+    if (o->nrhs[s] < 1 || o->nrhs[s] > (1 << 20)) return fail(REBK_ERR_INVALID, "nrhs[%d] must be in 1..2^20", s);
     if (!o->b_dev[s] || !o->x_out_dev[s]) return fail(REBK_ERR_INVALID, "b and x_out of system %d are NULL", s);
     if (o->x_ref_dev && !o->x_ref_dev[s]) return fail(REBK_ERR_INVALID, "x_ref of system %d is NULL", s);
     if (o->z_out_dev && !o->z_out_dev[s]) return fail(REBK_ERR_INVALID, "z_out of system %d is NULL", s);
@@ -1195,6 +1208,7 @@ extern "C" int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol,
 
 struct rebk_mlp {
   int32_t in = 0, hid = 0, max_batch = 0;
+  double out_scale = 1.0;  // x0 = out_scale A^T y
   int64_t out = 0, n = 0;
   hipStream_t stream = nullptr;
   int64_t t = 0;  // Adam steps taken
@@ -1208,6 +1222,8 @@ struct rebk_mlp {
   int64_t cnt[6] = {};
   _Float16* w16[3] = {};
   _Float16* A16 = nullptr;  // out x n
+  double* A64 = nullptr;    // out x n, for x0 = out_scale A^T y in FP64 at inference
+  double* Y64 = nullptr;    // max_batch x out
   // activations and signals for max_batch rows
   _Float16 *B16 = nullptr, *H1 = nullptr, *H2 = nullptr, *Y16 = nullptr, *R16 = nullptr, *DY16 = nullptr,
            *D2 = nullptr, *D1 = nullptr;
@@ -1240,7 +1256,8 @@ int mlp_forward_impl(rebk_mlp* w, const double* B, int32_t batch, double b_scale
   HIP_TRY(rebk::launch_gemm_f16(false, true, batch, out, hid, 1.f, w->H2, hid, w->w16[2], hid, 0.f, w->Y, out, st));
   HIP_TRY(rebk::launch_bias_act(w->Y, w->p[5], batch, out, 0, w->Y16, w->Y, st));
   // x0 = A^T y for every row: X0 = Y A
-  HIP_TRY(rebk::launch_gemm_f16(false, false, batch, n, out, 1.f, w->Y16, out, w->A16, n, 0.f, w->X0, n, st));
+  HIP_TRY(rebk::launch_gemm_f16(false, false, batch, n, out, (float)w->out_scale, w->Y16, out, w->A16, n, 0.f, w->X0, n,
+                                st));
   return REBK_OK;
 }
 
@@ -1255,7 +1272,7 @@ int mlp_check_batch(const rebk_mlp* w, int32_t batch) {
 extern "C" {
 
 int rebk_mlp_create(rebk_mlp_t* out, int32_t in_dim, int32_t hidden, const double* A_dev, int64_t out_dim, int64_t n,
-                    int32_t max_batch, uint64_t seed, void* stream) {
+                    double out_scale, int32_t max_batch, uint64_t seed, void* stream) {
   g_err[0] = 0;
   if (!out) return fail(REBK_ERR_INVALID, "out is NULL");
   *out = nullptr;
@@ -1264,6 +1281,7 @@ int rebk_mlp_create(rebk_mlp_t* out, int32_t in_dim, int32_t hidden, const doubl
       out_dim % 64 || n % 64 || max_batch % 64)
     return fail(REBK_ERR_INVALID, "in_dim, hidden, out_dim, n and max_batch must be positive multiples of 64");
   if (out_dim > (1 << 26) || in_dim > (1 << 26)) return fail(REBK_ERR_INVALID, "dimensions too large");
+  if (!(out_scale > 0.0) || !std::isfinite(out_scale)) return fail(REBK_ERR_INVALID, "out_scale must be positive");
   rebk_mlp* w = new (std::nothrow) rebk_mlp();
   if (!w) return fail(REBK_ERR_OOM, "host allocation failed");
   w->in = in_dim;
@@ -1271,6 +1289,7 @@ int rebk_mlp_create(rebk_mlp_t* out, int32_t in_dim, int32_t hidden, const doubl
   w->out = out_dim;
   w->n = n;
   w->max_batch = max_batch;
+  w->out_scale = out_scale;
   w->stream = (hipStream_t)stream;
   const int64_t cnt[6] = {(int64_t)hidden * in_dim, hidden, (int64_t)hidden * hidden, hidden, out_dim * hidden, out_dim};
   bool ok = true;
@@ -1281,7 +1300,8 @@ int rebk_mlp_create(rebk_mlp_t* out, int32_t in_dim, int32_t hidden, const doubl
   }
   for (int q = 0; q < 3; ++q) ok = ok && w->alloc(w->w16[q], cnt[2 * q]);
   const int64_t B = max_batch;
-  ok = ok && w->alloc(w->A16, out_dim * n) && w->alloc(w->B16, B * in_dim) && w->alloc(w->H1, B * hidden) &&
+  ok = ok && w->alloc(w->A16, out_dim * n) && w->alloc(w->A64, out_dim * n) && w->alloc(w->Y64, B * out_dim) &&
+       w->alloc(w->B16, B * in_dim) && w->alloc(w->H1, B * hidden) &&
        w->alloc(w->H2, B * hidden) && w->alloc(w->Y16, B * out_dim) && w->alloc(w->R16, B * n) &&
        w->alloc(w->DY16, B * out_dim) && w->alloc(w->D2, B * hidden) && w->alloc(w->D1, B * hidden) &&
        w->alloc(w->C, B * hidden) && w->alloc(w->Y, B * out_dim) && w->alloc(w->X0, B * n) && w->alloc(w->R, B * n) &&
@@ -1293,6 +1313,7 @@ int rebk_mlp_create(rebk_mlp_t* out, int32_t in_dim, int32_t hidden, const doubl
   }
   hipStream_t st = w->stream;
   hipError_t e = rebk::launch_to_half_f64(A_dev, out_dim * n, 1.0, w->A16, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w->A64, A_dev, out_dim * n * sizeof(double), hipMemcpyDeviceToDevice, st);
   // weights uniform in +-1/sqrt(fan_in) (Philox, seed), biases and moments zero
   const int fan[3] = {in_dim, hidden, hidden};
   for (int q = 0; q < 3 && e == hipSuccess; ++q) {
@@ -1350,8 +1371,12 @@ int rebk_mlp_forward(rebk_mlp_t w, const double* B_dev, int32_t batch, double b_
   if (rc != REBK_OK) return rc;
   rc = mlp_forward_impl(w, B_dev, batch, b_scale);
   if (rc != REBK_OK) return rc;
-  HIP_TRY(rebk::launch_widen(w->X0, (int64_t)batch * w->n, X0_dev, w->stream));
-  if (Y_dev) HIP_TRY(rebk::launch_widen(w->Y, (int64_t)batch * w->out, Y_dev, w->stream));
+  // x0 = out_scale A^T y in FP64 from the FP64 A: inside range(A^T) to FP64 rounding, which REBK
+  // needs to reach A^+ b (its x-steps never remove a component outside range(A^T))
+  double* Y64 = Y_dev ? Y_dev : w->Y64;
+  HIP_TRY(rebk::launch_widen(w->Y, (int64_t)batch * w->out, Y64, w->stream));
+  HIP_TRY(rebk::launch_gemm_f64(batch, (int)w->n, (int)w->out, w->out_scale, Y64, (int)w->out, w->A64, (int)w->n, X0_dev,
+                                (int)w->n, w->stream));
   HIP_TRY(hipStreamSynchronize(w->stream));
   return REBK_OK;
 }
@@ -1383,7 +1408,7 @@ int rebk_mlp_grad(rebk_mlp_t w, const double* B_dev, const double* Xt_dev, int32
   if (!std::isfinite(total)) return fail(REBK_ERR_INVALID, "the loss is not finite");
   // residual scaled by a power of two (largest magnitude in [4, 8]) before half rounding
   const double s = rmax > 0.0 ? std::ldexp(1.0, 3 - (int)std::ceil(std::log2(rmax))) : 1.0;
-  const float k = (float)(1.0 / (s * batch));
+  const float k = (float)(w->out_scale / (s * batch));
   HIP_TRY(rebk::launch_scale_half(w->R, rn, (float)s, w->R16, st));
   // dY = (s R) A^T
   HIP_TRY(rebk::launch_gemm_f16(false, true, batch, out, n, 1.f, w->R16, n, w->A16, n, 0.f, w->DY, out, st));

@@ -129,7 +129,7 @@ __host__ __device__ inline BatchLayout batch_layout(int64_t m, int64_t n, int R,
   L.v = L.x + (size_t)R * n;
   L.u = L.v + (size_t)R * max_nJ;
   L.ew = L.u + (size_t)R * max_nI;
-  L.total = L.ew + (size_t)R * ((threads + 63) / 64) + 2 * (size_t)R;
+  L.total = L.ew + 2 * (size_t)R * ((threads + 63) / 64) + 2 * (size_t)R;
   return L;
 }
 
@@ -144,7 +144,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
   double* v = lds + L.v;    // v[k * max_nJ + c]
   double* u = lds + L.u;    // u[k * max_nI + l]
   double* ew = lds + L.ew;  // per-wave partial errors, then R totals and R reference norms
-  double* etot = ew + (size_t)R * nw;
+  double* etot = ew + 2 * (size_t)R * nw;
   double* xr2 = etot + R;
   const int MJ = a.max_nJ, MI = a.max_nI;
   const GLOBAL_AS TP* __restrict__ Arow = gptr((const TP*)S.Arow);
@@ -187,6 +187,41 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
       }
 #pragma unroll
       for (int k = 0; k < R; ++k) z[k * m + l] = bvec[k * m + l] - acc[k];
+    }
+    __syncthreads();
+    // fallback: a start with ||b - A x0|| >= ||b|| is no better than x0 = 0; use x0 = 0, z0 = b
+    double zz[R], bb[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) zz[k] = bb[k] = 0.0;
+    for (int64_t l = tid; l < m; l += T) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const double zv = z[k * m + l], bv = bvec[k * m + l];
+        zz[k] += zv * zv;
+        bb[k] += bv * bv;
+      }
+    }
+    double* scratch = lds + L.ew;  // 2 R per wave (the error scratch is not in use yet)
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const double s1 = lane_group_sum(zz[k], 64), s2 = lane_group_sum(bb[k], 64);
+      if (lane == 0) {
+        scratch[(wid * R + k) * 2] = s1;
+        scratch[(wid * R + k) * 2 + 1] = s2;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      double tz = 0.0, tb = 0.0;
+      for (int q = 0; q < nw; ++q) {
+        tz += scratch[(q * R + k) * 2];
+        tb += scratch[(q * R + k) * 2 + 1];
+      }
+      if (!(tz < tb)) {  // uniform across the workgroup
+        for (int64_t c = tid; c < n; c += T) x[k * n + c] = 0.0;
+        for (int64_t l = tid; l < m; l += T) z[k * m + l] = bvec[k * m + l];
+      }
     }
     __syncthreads();
   }

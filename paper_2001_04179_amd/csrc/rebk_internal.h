@@ -167,6 +167,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t cou
                        float eps, float c1, float c2, _Float16* p16, hipStream_t st);
 hipError_t launch_init_uniform(float* p, int64_t count, float bound, uint64_t seed, uint64_t tag, hipStream_t st);
 hipError_t launch_widen(const float* in, int64_t count, double* out, hipStream_t st);
+hipError_t launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,
+                           double* C, int ldc, hipStream_t st);
 
 // refinement kernels (FP64, caller's row-major A with leading dimension lda)
 int64_t refine_chunks(int64_t m);  // row chunks of the transposed product (partial: chunks x n doubles)

@@ -200,6 +200,26 @@ __global__ void widen_kernel(const float* __restrict__ in, int64_t count, double
     out[e] = (double)in[e];
 }
 
+// C (M x N, FP64) = alpha * A (M x K) B (K x N), all FP64 row-major; 16 x 16 tiles, K in steps of
+// 16 through LDS.  Forms x0 = out_scale A^T y exactly (to FP64 rounding) in range(A^T).
+__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                       int lda, const double* __restrict__ B, int ldb,
+                                                       double* __restrict__ C, int ldc) {
+  __shared__ double As[16][17], Bs[16][17];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    As[ty][tx] = (row < M && k0 + tx < K) ? A[(size_t)row * lda + k0 + tx] : 0.0;
+    Bs[ty][tx] = (k0 + ty < K && col < N) ? B[(size_t)(k0 + ty) * ldb + col] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += As[ty][k] * Bs[k][tx];
+    __syncthreads();
+  }
+  if (row < M && col < N) C[(size_t)row * ldc + col] = alpha * acc;
+}
+
 unsigned blocks_for(int64_t count) {
   const int64_t g = (count + 255) / 256;
   return (unsigned)(g < 8192 ? (g > 0 ? g : 1) : 8192);
@@ -259,6 +279,13 @@ hipError_t launch_init_uniform(float* p, int64_t count, float bound, uint64_t se
   hipLaunchKernelGGL(init_uniform_kernel, dim3(blocks_for(count)), dim3(256), 0, st, p, count, bound, seed, tag);
   return hipGetLastError();
 }
+hipError_t launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,
+                           double* C, int ldc, hipStream_t st) {
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((N + 15) / 16, (M + 15) / 16), dim3(256), 0, st, M, N, K, alpha, A, lda, B,
+                     ldb, C, ldc);
+  return hipGetLastError();
+}
+
 hipError_t launch_widen(const float* in, int64_t count, double* out, hipStream_t st) {
   hipLaunchKernelGGL(widen_kernel, dim3(blocks_for(count)), dim3(256), 0, st, in, count, out);
   return hipGetLastError();

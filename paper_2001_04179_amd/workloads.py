@@ -175,6 +175,57 @@ def rank1200_2000x50000(rng_seed=1003, seed=0, scale: int = 1) -> System:
     return factor_product(m, n, r, rng_seed=rng_seed, noise=0.1, row_tau=100, col_tau=100, alpha_c=1.0, seed=seed)
 
 
+def warmstart_problem(n_train=65536, n_eval=4096, rng_seed=1005, m=8192, n=1024, rank=768, n_basis=8, n_freq=16,
+                      noise=0.05, row_tau=64, col_tau=16, device="cuda", chunk=8192):
+    """The learned-warm-start workload.  A = U V / sqrt(rank) (U m x rank, V rank x n, N(0,1));
+    right-hand sides b = A x(theta) + r with theta ~ U[-1, 1]^8, x(theta) = sum_k theta_k phi_k over
+    fixed smooth bases phi_k(t) = sum_{f=1}^{16} a_kf cos(pi f t + psi_kf) on 1024 points of [0, 1]
+    (a_kf ~ N(0, 1/f^2), psi_kf ~ U[0, 2 pi)), r = (I - P_range(A)) g scaled to 0.05 ||A x||;
+    references x_ref = P_range(A^T) x(theta) = A^+ b.  The factorisations run on the host (numpy,
+    seed rng_seed); the right-hand sides are generated on the device in chunks with a seeded
+    torch generator (inputs only).  Returns a dict of device tensors and host metadata."""
+    import torch
+    rng = np.random.default_rng(rng_seed)
+    U = rng.standard_normal((m, rank))
+    V = rng.standard_normal((rank, n))
+    A = (U @ V) / np.sqrt(rank)
+    Qu = orthonormal(U)
+    Qv = orthonormal(V.T)
+    t = np.linspace(0.0, 1.0, n)
+    f = np.arange(1, n_freq + 1)
+    a = rng.standard_normal((n_basis, n_freq)) / f
+    psi = rng.uniform(0.0, 2.0 * np.pi, (n_basis, n_freq))
+    Phi = np.einsum("kf,kft->kt", a, np.cos(np.pi * f[None, :, None] * t[None, None, :] + psi[:, :, None]))
+    ro = contiguous_offsets(m, row_tau)
+    co = contiguous_offsets(n, col_tau)
+    br, bc = beta_max(A, ro, co)
+    dev = torch.device(device)
+    A_d = torch.from_numpy(A).to(dev)
+    Qu_d, Qv_d, Phi_d = (torch.from_numpy(v).to(dev) for v in (Qu, Qv, Phi))
+    gen = torch.Generator(device=dev).manual_seed(rng_seed)
+
+    def rhs(N):
+        B = torch.empty((N, m), dtype=torch.float64, device=dev)
+        X = torch.empty((N, n), dtype=torch.float64, device=dev)
+        for c0 in range(0, N, chunk):
+            c1 = min(N, c0 + chunk)
+            theta = torch.rand((c1 - c0, n_basis), generator=gen, device=dev, dtype=torch.float64) * 2.0 - 1.0
+            Xs = theta @ Phi_d
+            AX = Xs @ A_d.T
+            G = torch.randn((c1 - c0, m), generator=gen, device=dev, dtype=torch.float64)
+            Rn = G - (G @ Qu_d) @ Qu_d.T
+            Rn *= (noise * AX.norm(dim=1) / Rn.norm(dim=1)).unsqueeze(1)
+            B[c0:c1] = AX + Rn
+            X[c0:c1] = (Xs @ Qv_d) @ Qv_d.T
+        return B, X
+
+    B_tr, X_tr = rhs(n_train)
+    B_ev, X_ev = rhs(n_eval)
+    return {"A": A, "A_dev": A_d, "row_off": ro, "col_off": co, "alpha": 1.0 / max(br, bc), "beta_row": br,
+            "beta_col": bc, "B_train": B_tr, "X_train_ref": X_tr, "B_eval": B_ev, "X_eval_ref": X_ev,
+            "rank": rank}
+
+
 @dataclass
 class BatchSystem:
     """One system of a batch with several right-hand sides (rows of B, X_ref)."""
