@@ -230,11 +230,10 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   if (h->max_nJ > rebk::kGridThreads)
     return fail(REBK_ERR_INVALID, "column blocks wider than %d columns need the one-workgroup kernel", rebk::kGridThreads);
   rebk::GridSync gs{};
-  gs.groups = G < 16 ? G : 16;
-  if (G > 64 * gs.groups) return fail(REBK_ERR_INVALID, "at most %d workgroups in the grid kernel", 64 * gs.groups);
+  if (G > 1024) return fail(REBK_ERR_INVALID, "at most 1024 workgroups in the grid kernel");
   gs.stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
   const size_t part_words = (size_t)2 * G * gs.stride * 2;
-  const size_t gsum_words = (size_t)32 * gs.groups * gs.stride * 2;  // ring of 32 epochs
+  const size_t gsum_words = (size_t)rebk::kGridSumRing * rebk::kGridSumCopies * gs.stride * 2;
   int rc = ensure_grid_workspace(h, part_words, gsum_words);
   if (rc != REBK_OK) return rc;
   gs.part = h->part;

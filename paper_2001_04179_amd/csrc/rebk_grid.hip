@@ -9,15 +9,16 @@
 // The z-chain never reads x, so running the x-chain one iteration behind the z-chain is exact and
 // needs a single synchronisation per iteration.
 //
-// Reduction: a deterministic two-level tree without counters or fences.  Every value crossing
-// workgroups is published as two 64-bit atomic words that both carry the iteration's epoch, so a
-// reader can tell a current value from a stale or half-written one.  Workgroup w belongs to group
-// g = w mod NG, whose leader is workgroup g: the leader polls its members' tagged partial vectors,
-// sums them in member order and publishes the tagged group sum; every workgroup waits for the NG
-// group sums and adds them in group order.  All workgroups therefore see bit-identical reduced
-// vectors and a run is reproducible bit for bit.  All cross-workgroup traffic uses device-scope
-// atomic loads and stores, coherent across the eight XCDs without cache maintenance (an
-// agent-scope release fence writes back the XCD's L2 and costs microseconds on gfx950).
+// Reduction: a deterministic reduce-scatter and all-gather without counters or fences.  Every
+// value crossing workgroups is published as two 64-bit atomic words that both carry the
+// iteration's epoch, so a reader can tell a current value from a stale or half-written one.  The
+// partial vector is cut into chunks of 8 entries; workgroup c owns chunk c (c, c + G, ... for
+// long vectors): it polls that chunk of every workgroup's partial vector, sums the G partials in
+// a fixed order and publishes the tagged sums.  Every workgroup then reads the reduced vector
+// once.  Each sum is formed by one workgroup, so all workgroups see bit-identical reduced vectors
+// and a run is reproducible bit for bit.  All cross-workgroup traffic uses device-scope atomic
+// loads and stores, coherent across the eight XCDs without cache maintenance (an agent-scope
+// release fence writes back the XCD's L2 and costs microseconds on gfx950).
 //
 // Panel slabs: the column slab A_{R_w, J} (owned rows; column panels hold A^T, so the slab is |J|
 // runs of the owned rows) and the row slab A_{I, C_w} (owned columns, contiguous in the
@@ -37,7 +38,16 @@ namespace {
 using namespace dev;
 
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
-constexpr int kSumRing = 32;                // group-sum buffers, one per epoch modulo the ring
+// Entries per reduction chunk (1, 2, 4 or 8).  Smaller chunks mean more owners, each polling fewer
+// bytes per round; on the 20000 x 2000 workload 2 was fastest (8: +13%, 4: +6%, 1: +2% per iteration).
+constexpr int kChunk = 2;
+static_assert(kChunk == 1 || kChunk == 2 || kChunk == 4 || kChunk == 8, "chunk of 1, 2, 4 or 8 entries");
+constexpr int kCopies = kGridSumCopies;     // copies of the reduced vector
+
+template <int N>
+struct Count {
+  static constexpr int value = N;
+};
 
 __device__ __forceinline__ unsigned long long ld_u64(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -54,13 +64,18 @@ __device__ __forceinline__ void st_u64(unsigned long long* p, unsigned long long
 // A value published for one epoch: two 64-bit atomic words, each carrying the 32-bit epoch next
 // to one half of the FP64 bit pattern.  A reader accepts the pair only when both words carry the
 // epoch it waits for, so it never takes a stale value or a pair torn between two epochs; no fence
-// or counter is needed to order the data with its arrival.  A vector of E tagged values is stored
-// as two planes (first words at p[0, E), second words at p[E, 2E)), so the lanes of one store or
-// load instruction touch consecutive words.
-__device__ __forceinline__ void st_tagged(unsigned long long* p, int E, int e, double v, unsigned epoch) {
+// or counter is needed to order the data with its arrival.  A vector of tagged values is stored
+// in chunks of kChunk entries, each a run of 2 kChunk words: the first words of the entries in
+// entry order, then their second words in reverse order, so that the word pairs of a run sit
+// mirror-symmetrically and lane p of a run finds its partner in lane 2 kChunk - 1 - p.
+__device__ __forceinline__ int tag_word(int e, int plane) {
+  const int j = e % kChunk, run = (e / kChunk) * 2 * kChunk;
+  return plane == 0 ? run + j : run + 2 * kChunk - 1 - j;
+}
+__device__ __forceinline__ void st_tagged(unsigned long long* p, int e, double v, unsigned epoch) {
   const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-  st_u64(p + e, ((unsigned long long)epoch << 32) | (bits >> 32));
-  st_u64(p + E + e, (bits << 32) | (unsigned long long)epoch);
+  st_u64(p + tag_word(e, 0), ((unsigned long long)epoch << 32) | (bits >> 32));
+  st_u64(p + tag_word(e, 1), (bits << 32) | (unsigned long long)epoch);
 }
 __device__ __forceinline__ bool tag_ok(unsigned long long w0, unsigned long long w1, unsigned epoch) {
   return (unsigned)(w0 >> 32) == epoch && (unsigned)w1 == epoch;
@@ -115,6 +130,16 @@ __device__ __forceinline__ double dpp_f64(double x) {
   return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
                           __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
 }
+// The word held by the mirror lane of this lane's run of 2 kChunk lanes (lane p <-> 2 kChunk - 1 - p):
+// a data-parallel-primitive move (row mirror for runs of 16, half-row mirror for 8, reversed quad
+// for 4, swapped pairs for 2).
+__device__ __forceinline__ unsigned long long mirror_word(unsigned long long x) {
+  constexpr int ctrl = kChunk == 8 ? 0x140 : (kChunk == 4 ? 0x141 : (kChunk == 2 ? 0x1B : 0xB1));
+  const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
+  const unsigned nlo = (unsigned)__builtin_amdgcn_update_dpp(0, lo, ctrl, 0xF, 0xF, false);
+  const unsigned nhi = (unsigned)__builtin_amdgcn_update_dpp(0, hi, ctrl, 0xF, 0xF, false);
+  return ((unsigned long long)nhi << 32) | nlo;
+}
 // Sum over aligned groups of `width` lanes (a power of two <= 64); every lane of a group gets the
 // group's sum.  Quad permutations, half-row and row mirrors stay inside a row of 16 lanes.
 __device__ __forceinline__ double group_sum(double v, int width) {
@@ -165,6 +190,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   __shared__ int64_t s_c0[kRing], s_r0[kRing];
   __shared__ double s_cc[kRing], s_cr[kRing];
   __shared__ int s_ok;
+  __shared__ double s_red[(kGridThreads / 64) * kChunk];
   __shared__ double s_err2;
   const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
   const int64_t m = a.m, n = a.n;
@@ -187,11 +213,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 
   const TP* __restrict__ Arow = (const TP*)a.Arow;
   const TP* __restrict__ Acol = (const TP*)a.Acol;
-  const int NG = gs.groups, g = w % NG;
-  const int gsize = (G - g + NG - 1) / NG;
   const int E = gs.stride;
+  const int NCH = E / kChunk;  // reduction chunks; workgroup c owns chunks c, c + G, ...
   const int err_slot = MJ + MI;
-  const bool leader = w < NG;  // workgroup g collects group g
   const int64_t K = a.max_iter;
   const int64_t ce = a.check_every > 0 ? a.check_every : 1;
   const bool checking = a.x_ref != nullptr && a.tol > 0.0;
@@ -294,15 +318,25 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   };
 
   // One grid-wide reduction of this round's partial vectors (entries [0, nq), [MJ, MJ + np) and,
-  // with has_err, err_slot; every workgroup has published them tagged with `epoch`).  The leader
-  // of each group polls its members' tagged entries, sums them in member order and publishes the
-  // tagged group sum; every workgroup then waits for the group sums and adds them in group order.
-  // While the sums travel, waves 1..3 load the next round's slabs (column slab of iteration qc
-  // into column buffer bufC, row slab of iteration qr into row buffer bufR).  On return v, u and
-  // s_err2 hold the reduced values.  Returns false after a spin-limit timeout.
+  // with has_err, err_slot; every workgroup has published them tagged with `epoch`), in two
+  // steps, while waves 1..3 copy the next round's slabs (column slab of iteration qc into column
+  // buffer bufC, row slab of iteration qr into row buffer bufR) straight into LDS.
+  //   1. Workgroup c owns chunk c (and c + G, ...) of the vectors: all its waves poll that chunk of
+  //      every workgroup's partial vector (2 kChunk lanes read one workgroup's run), add the G
+  //      partials in a fixed order (per lane over its workgroups, across the lane groups of the
+  //      wave, then across the waves) and publish the tagged sums in kCopies copies.  Owners
+  //      start their slab copies afterwards: a wave's loads complete in order, so polls issued
+  //      behind the copies would wait for them.
+  //   2. Wave 0 of every workgroup reads the reduced vector from copy w mod kCopies into v, u and
+  //      s_err2; the copies spread the readers over more memory channels.
+  // Returns false after a spin-limit timeout.
   auto need = [&](int e, int nq, int np, bool has_err) -> bool {
     return e < nq || (e >= MJ && e < MJ + np) || (has_err && e == err_slot);
   };
+  constexpr int K2 = 2 * kChunk;  // lanes (words) per chunk run
+  const int p2 = tid & (K2 - 1);  // this lane's word in a run
+  const bool first = p2 < kChunk;  // lane holds a first word; its entry is p2 (else K2 - 1 - p2)
+  const int je = first ? p2 : K2 - 1 - p2;
   auto sync_round = [&](unsigned epoch, int par, int nq, int np, bool has_err, int64_t qc, int bufC, int64_t qr,
                         int bufR) -> bool {
     int ok = 1;
@@ -318,100 +352,120 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
       }
       return false;
     };
-    const bool any = nq > 0 || np > 0 || has_err;
-    if (leader && any) {
-      const unsigned long long* P = gs.part + (size_t)par * G * E * 2;
-      unsigned long long* Gs = gs.gsum + ((size_t)(epoch % kSumRing) * NG + g) * E * 2;
-      for (int e = tid; e < E && ok; e += T) {
-        if (!need(e, nq, np, has_err)) continue;
-        double s = 0.0;  // member order g, g + NG, ...
-        for (int q0 = 0; q0 < gsize && ok; q0 += 16) {
-          const int cnt = gsize - q0 < 16 ? gsize - q0 : 16;
-          unsigned pending = (1u << cnt) - 1u;
-          double vals[16];
-          while (pending) {
-            unsigned long long w0[16], w1[16];
+    // Poll N runs per lane (run k at addr(k), this lane's word p2) until every value marked in
+    // `pending` carries the epoch; vals[k] receives this lane's entry of run k.  The whole wave
+    // runs the loop: the lanes of a run exchange words.
+    auto poll_runs = [&](auto count, auto addr, unsigned pending, double* vals) {
+      constexpr int N = decltype(count)::value;
+      while (ok) {
+        unsigned long long wd[N];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-              const int qq = q0 + q < gsize ? q0 + q : gsize - 1;
-              const unsigned long long* src = P + (size_t)(g + qq * NG) * E * 2 + e;
-              w0[q] = ld_u64(src);
-              w1[q] = ld_u64(src + E);
-            }
+        for (int k = 0; k < N; ++k) wd[k] = ld_u64(addr(k) + p2);
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-              if (((pending >> q) & 1u) && tag_ok(w0[q], w1[q], epoch)) {
-                vals[q] = tag_value(w0[q], w1[q]);
-                pending &= ~(1u << q);
-              }
-            if (pending && give_up()) { ok = 0; break; }
+        for (int k = 0; k < N; ++k) {
+          const unsigned long long o = mirror_word(wd[k]);
+          const unsigned long long w0 = first ? wd[k] : o, w1 = first ? o : wd[k];
+          if (((pending >> k) & 1u) && tag_ok(w0, w1, epoch)) {
+            vals[k] = tag_value(w0, w1);
+            pending &= ~(1u << k);
           }
-#pragma unroll
-          for (int q = 0; q < 16; ++q) s += (q < cnt) ? vals[q] : 0.0;
         }
-        st_tagged(Gs, E, e, s, epoch);
+        if (!__any(pending != 0)) break;
+        if (give_up()) ok = 0;
       }
-    }
+    };
+    const bool any = nq > 0 || np > 0 || has_err;
     const Src sr = slab_src(qc, qr);
     TP* dC = slabC + (size_t)bufC * L.slabC;
     TP* dR = RowLds ? slabR + (size_t)bufR * L.slabR : slabR;
     const bool okC = dma_ok(sr.c, a.ldc, sr.runs, nr, dC);
     const bool okR = dma_ok(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
-    if (tid >= 64) {  // waves 1..3: start the copies of the next slabs straight into LDS
-      if (okC) dma_runs(sr.c, a.ldc, sr.runs, nr, dC);
-      if (okR) dma_runs(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
-    }
-    const unsigned long long* Gall = gs.gsum + (size_t)(epoch % kSumRing) * NG * E * 2;
-    // wave 0 watches one entry of every group (the highest one reduced this round)
-    if (tid < 64 && any) {
-      const int ed = has_err ? err_slot : (np > 0 ? MJ + np - 1 : nq - 1);
-      bool seen = tid >= NG;
-      while (ok) {
-        if (!seen) {
-          const unsigned long long* src = Gall + (size_t)tid * E * 2 + ed;
-          const unsigned long long w0 = ld_u64(src), w1 = ld_u64(src + E);
-          seen = tag_ok(w0, w1, epoch);
-        }
-        if (__all(seen)) break;
-        if (give_up()) ok = 0;
+    auto start_copies = [&]() {  // waves 1..3: the next slabs, straight into LDS
+      if (tid >= 64) {
+        if (okC) dma_runs(sr.c, a.ldc, sr.runs, nr, dC);
+        if (okR) dma_runs(sr.r, 0, sr.lr > 0 ? 1 : 0, sr.lr, dR);
       }
-      if (!ok) s_ok = 0;
-    }
-    __syncthreads();
-    if (s_ok == 0) ok = 0;
-    // every needed entry: the NG tagged group sums, added in group order.  The first read goes
-    // through the XCD's L2 (workgroup-scope loads), so the 32 workgroups of an XCD fetch the
-    // group sums from memory once; a pair whose tag is not current (a stale cached line, or a
-    // late store) is re-read at device scope until it is.
-    for (int e = tid; e < E && ok; e += T) {
-      if (!need(e, nq, np, has_err)) continue;
-      double vals[16];
-      unsigned pending = (1u << NG) - 1u;
-      bool cached = true;
-      while (pending) {
-        unsigned long long w0[16], w1[16];
+    };
+    const bool owner = any && w < NCH;
+    if (!owner) start_copies();
+    const int lane = tid & 63;
+    const size_t V2 = (size_t)E * 2;
+    unsigned long long* Sring = gs.gsum + (size_t)(epoch % kGridSumRing) * kCopies * V2;
+    if (owner) {
+      const unsigned long long* P = gs.part + (size_t)par * G * V2;
+      constexpr int kRuns = K2;                // runs per lane per pass
+      const int rows = T / K2, row = tid / K2;  // workgroups read per load step of the workgroup
+      for (int c = w; c < NCH; c += G) {  // uniform over the workgroup
+        const int e0 = c * kChunk;
+        bool chunk_needed = false;
+        for (int j = 0; j < kChunk; ++j) chunk_needed |= need(e0 + j, nq, np, has_err);
+        if (!chunk_needed) continue;
+        const bool mine = first && need(e0 + je, nq, np, has_err);
+        double acc = 0.0;
+        for (int mb0 = 0; mb0 < G; mb0 += kRuns * rows) {
+          unsigned pending = 0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const unsigned long long* src = Gall + (size_t)(q < NG ? q : NG - 1) * E * 2 + e;
-          w0[q] = cached ? ld_u64_cached(src) : ld_u64(src);
-          w1[q] = cached ? ld_u64_cached(src + E) : ld_u64(src + E);
+          for (int k = 0; k < kRuns; ++k)
+            if (mine && mb0 + k * rows + row < G) pending |= 1u << k;
+          double vals[kRuns];
+          poll_runs(Count<kRuns>{}, [&](int k) {
+            int mb = mb0 + k * rows + row;
+            mb = mb < G ? mb : G - 1;
+            return P + (size_t)mb * V2 + (size_t)c * K2;
+          }, pending, vals);
+#pragma unroll
+          for (int k = 0; k < kRuns; ++k)
+            if (mine && mb0 + k * rows + row < G) acc += vals[k];
         }
-        cached = false;
+        // lanes p2 < kChunk hold entry e0 + p2 summed over their workgroups: add the lane groups
+        // of the wave (butterfly: every lane gets the same sum), then the waves in order
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (((pending >> q) & 1u) && tag_ok(w0[q], w1[q], epoch)) {
-            vals[q] = tag_value(w0[q], w1[q]);
-            pending &= ~(1u << q);
+        for (int o = K2; o < 64; o *= 2) acc += __shfl_xor(acc, o, 64);
+        if (lane < kChunk) s_red[(tid >> 6) * kChunk + lane] = acc;
+        __syncthreads();
+        if (tid < kChunk * kCopies) {
+          const int j = tid % kChunk, cp = tid / kChunk;
+          if (need(e0 + j, nq, np, has_err)) {
+            double t = 0.0;
+            for (int q = 0; q < (T >> 6); ++q) t += s_red[q * kChunk + j];
+            st_tagged(Sring + (size_t)cp * V2, e0 + j, t, epoch);
           }
-        if (pending && give_up()) { ok = 0; break; }
+        }
+        __syncthreads();
       }
-      if (!ok) break;
-      double s = 0.0;
+      start_copies();
+    }
+    // step 2 (wave 0): the reduced vector, 64 / K2 chunks per load instruction
+    if (tid < 64 && any) {
+      const unsigned long long* Sg = Sring + (size_t)(w % kCopies) * V2;
+      constexpr int kPer = 64 / K2;  // chunks per load instruction
+      const int r = lane / K2;
+      for (int cb = 0; cb < NCH; cb += 8 * kPer) {  // up to 8 load instructions per pass
+        unsigned pending = 0;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) s += (q < NG) ? vals[q] : 0.0;
-      if (e < MJ) v[e] = s;
-      else if (e < MJ + MI) u[e - MJ] = s;
-      else s_err2 = s;
+        for (int k = 0; k < 8; ++k) {
+          const int c = cb + kPer * k + r;
+          if (c < NCH && first && need(c * kChunk + je, nq, np, has_err)) pending |= 1u << k;
+        }
+        double vals[8];
+        poll_runs(Count<8>{}, [&](int k) {
+          int c = cb + kPer * k + r;
+          c = c < NCH ? c : NCH - 1;
+          return Sg + (size_t)c * K2;
+        }, pending, vals);
+        if (ok && first) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int c = cb + kPer * k + r;
+            const int e = c * kChunk + je;
+            if (c < NCH && need(e, nq, np, has_err)) {
+              if (e < MJ) v[e] = vals[k];
+              else if (e < MJ + MI) u[e - MJ] = vals[k];
+              else s_err2 = vals[k];
+            }
+          }
+        }
+      }
     }
     // slabs of 2-byte panels that are not whole aligned dwords are copied with ordinary loads;
     // then wait for the copies this wave started
@@ -477,7 +531,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         if (q < nr) a0 += widen(col[q]) * z[q];
       }
       const double acc = group_sum(a0 + a1, tq);
-      if (c < nJ && sub == 0) st_tagged(P, E, c, acc, ep);
+      if (c < nJ && sub == 0) st_tagged(P, c, acc, ep);
     }
   };
   // partial error ||x - x_ref||^2 over owned columns (wave 0)
@@ -489,7 +543,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         e += d * d;
       }
       e = wave_sum(e);
-      if (tid == 0) st_tagged(P, E, err_slot, e, ep);
+      if (tid == 0) st_tagged(P, err_slot, e, ep);
     }
   };
 
@@ -553,7 +607,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         }
         const int64_t gl = rI + l;
         if (gl >= r0 && gl < r1) acc += z[gl - r0] - bl[gl - r0];
-        st_tagged(P, E, MJ + l, acc, ep);
+        st_tagged(P, MJ + l, acc, ep);
       }
     }
     if (has_err) err_partial(P, ep);

@@ -52,12 +52,13 @@ struct SolveArgs {
 };
 
 // Synchronisation workspace of the persistent grid kernel (zeroed before every launch).
+constexpr int kGridSumRing = 4;    // reduced vectors kept, one per epoch modulo the ring
+constexpr int kGridSumCopies = 8;  // copies of each reduced vector (spread over memory channels)
 struct GridSync {
-  unsigned long long* part;  // 2 x grid vectors of stride epoch-tagged pairs (two planes of stride words)
-  unsigned long long* gsum;  // 32 x groups vectors of stride tagged pairs: per-group sums (ring)
+  unsigned long long* part;  // 2 x grid vectors of stride epoch-tagged pairs (2 * stride words each)
+  unsigned long long* gsum;  // kGridSumRing x kGridSumCopies reduced vectors (stride tagged pairs)
   int* timeout;              // set when a wait exceeded its spin limit
-  int32_t stride;            // entries per partial vector (>= max_nJ + max_nI + 1)
-  int32_t groups;            // reduction groups (<= 16)
+  int32_t stride;            // entries per vector (>= max_nJ + max_nI + 1, a multiple of 32)
 };
 
 // One system of a batch: its panels, tables and Philox stream (device copy of the handle's data).
