@@ -88,12 +88,6 @@ __device__ __forceinline__ double tag_value(unsigned long long w0, unsigned long
 // the memory clobber keeps the compiler from moving accesses across.
 __device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-
 struct GridLayout {
   int NR, NC;     // max rows / columns owned by one workgroup
   size_t dbl;     // doubles before the panel slabs
@@ -219,7 +213,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   const int64_t K = a.max_iter;
   const int64_t ce = a.check_every > 0 ? a.check_every : 1;
   const bool checking = a.x_ref != nullptr && a.tol > 0.0;
-  const int tpc = lanes_per_item(T, nc);  // lanes per owned column in the x-update
+  const int kHalf = T / 2;  // waves 0-1: z side, waves 2-3: x side
 
   for (int q = tid; q < nr; q += T) {
     z[q] = a.z_in ? a.z_in[r0 + q] : a.b[r0 + q];
@@ -300,12 +294,12 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     __syncthreads();
   };
   // refinement: y_I -= coef_I u^q on the owned rows of I_q (the x-step is x -= A_I^T (coef_I u))
-  auto yupdate = [&](int64_t q) {
+  auto yupdate = [&](int64_t q, int lt, int nt) {
     const int sl = slot(q);
     const int64_t rI = s_r0[sl], rE = rI + s_nI[sl];
     const int64_t lo = rI > r0 ? rI : r0, hi = rE < r1 ? rE : r1;
     const double cr = s_cr[sl];
-    for (int64_t l = lo + tid; l < hi; l += T) yv[l - r0] -= cr * u[l - rI];
+    for (int64_t l = lo + lt; l < hi; l += nt) yv[l - r0] -= cr * u[l - rI];
   };
   auto copy_plain = [&](const Src& sr, TP* dC, TP* dR) {  // every thread, ordinary loads; NULL: skip
     if (dC)
@@ -477,28 +471,40 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     return all_ok;
   };
 
+  // The steps below run on threads [t0, t0 + nt) of the workgroup (whole waves), given as the
+  // local index lt = tid - t0 and nt: in the iteration loop the z-side steps run on waves 0-1 and
+  // the x-side steps on waves 2-3, at the same time.
   // z <- z - coef * A_{R,J} v on owned rows (slab entry (q, c) at c * nr + q); keeps the previous z.
-  auto zupdate = [&](const TP* Sl, int nJ, double coef) {
-    for (int q = tid; q < nr; q += T) {
+  auto zupdate = [&](const TP* Sl, int nJ, double coef, int lt, int nt) {
+    for (int q = lt; q < nr; q += nt) {
       const TP* row = Sl + q;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
       int c = 0;
-      for (; c + 3 < nJ; c += 4) {
+      for (; c + 7 < nJ; c += 8) {  // eight independent chains
         a0 += widen(row[(c + 0) * nr]) * v[c + 0];
         a1 += widen(row[(c + 1) * nr]) * v[c + 1];
         a2 += widen(row[(c + 2) * nr]) * v[c + 2];
         a3 += widen(row[(c + 3) * nr]) * v[c + 3];
+        a4 += widen(row[(c + 4) * nr]) * v[c + 4];
+        a5 += widen(row[(c + 5) * nr]) * v[c + 5];
+        a6 += widen(row[(c + 6) * nr]) * v[c + 6];
+        a7 += widen(row[(c + 7) * nr]) * v[c + 7];
       }
       for (; c < nJ; ++c) a0 += widen(row[c * nr]) * v[c];
+      a0 += a4;
+      a1 += a5;
+      a2 += a6;
+      a3 += a7;
       zp[q] = z[q];
       z[q] -= coef * ((a0 + a1) + (a2 + a3));
     }
   };
   // x <- x - coef * A_{I,C}^T u on owned columns (column-major slab nc x nI)
-  auto xupdate = [&](const TP* Sl, int nI, double coef) {
-    const int cp = T / tpc, sub = tid % tpc;
+  auto xupdate = [&](const TP* Sl, int nI, double coef, int lt, int nt) {
+    const int tpc = lanes_per_item(nt, nc);  // lanes per owned column
+    const int cp = nt / tpc, sub = lt % tpc;
     for (int c0 = 0; c0 < nc; c0 += cp) {
-      const int cc = c0 + tid / tpc;
+      const int cc = c0 + lt / tpc;
       double acc = 0.0;
       if (cc < nc) {
         const TP* col = Sl + (size_t)cc * nI;
@@ -516,35 +522,38 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   };
   // publish A_{R,J}^T z over owned rows (slab entry (q, c) at c * nr + q) as entries [0, nJ):
   // tq lanes per column, partial sums meet with lane exchanges
-  auto push_q = [&](const TP* Sl, int nJ, unsigned long long* P, unsigned ep) {
-    const int tq = lanes_per_item(T, nJ), per = T / tq, sub = tid % tq;
+  auto push_q = [&](const TP* Sl, int nJ, unsigned long long* P, unsigned ep, int lt, int nt) {
+    const int tq = lanes_per_item(nt, nJ), per = nt / tq, sub = lt % tq;
     for (int c0 = 0; c0 < nJ; c0 += per) {
-      const int c = c0 + tid / tq;
-      double a0 = 0.0, a1 = 0.0;
+      const int c = c0 + lt / tq;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       if (c < nJ) {
         const TP* col = Sl + (size_t)c * nr;
         int q = sub;
-        for (; q + tq < nr; q += 2 * tq) {
+        for (; q + 3 * tq < nr; q += 4 * tq) {  // four independent chains
           a0 += widen(col[q]) * z[q];
           a1 += widen(col[q + tq]) * z[q + tq];
+          a2 += widen(col[q + 2 * tq]) * z[q + 2 * tq];
+          a3 += widen(col[q + 3 * tq]) * z[q + 3 * tq];
         }
-        if (q < nr) a0 += widen(col[q]) * z[q];
+        for (; q < nr; q += tq) a0 += widen(col[q]) * z[q];
       }
-      const double acc = group_sum(a0 + a1, tq);
+      const double acc = group_sum((a0 + a1) + (a2 + a3), tq);
       if (c < nJ && sub == 0) st_tagged(P, c, acc, ep);
     }
   };
-  // partial error ||x - x_ref||^2 over owned columns (wave 0)
+  // partial error ||x - x_ref||^2 over owned columns (one whole wave calls it)
   auto err_partial = [&](unsigned long long* P, unsigned ep) {
-    if (tid < 64) {
-      double e = 0.0;
-      for (int cc = tid; cc < nc; cc += 64) {
-        const double d = x[cc] - xr[cc];
-        e += d * d;
-      }
-      e = wave_sum(e);
-      if (tid == 0) st_tagged(P, err_slot, e, ep);
+    const int lane = tid & 63;
+    double e = 0.0;
+    for (int cc = lane; cc < nc; cc += 64) {
+      const double d = x[cc] - xr[cc];
+      e += d * d;
     }
+    int width = 1;
+    while (width < nc && width < 64) width *= 2;
+    e = group_sum(e, width);
+    if (lane == 0) st_tagged(P, err_slot, e, ep);
   };
 
   unsigned epoch = 0;
@@ -560,7 +569,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     copy_plain(slab_src(1, 0), d1, nullptr);
     __syncthreads();
     const int nJ1 = s_nJ[slot(1)];
-    push_q(d1, nJ1, gs.part + (size_t)w * E * 2, epoch + 1);
+    push_q(d1, nJ1, gs.part + (size_t)w * E * 2, epoch + 1, tid, T);
     alive = sync_round(++epoch, 0, nJ1, 0, false, K >= 2 ? 2 : 0, 0, 1, 1);
     if (alive) apply_g(1);
   }
@@ -583,20 +592,25 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
     }
 
     // phase A: z^k on owned rows (column slab of J_k); x^{k-1} on owned columns (row slab of I_{k-1})
-    zupdate(slabC + (size_t)(rr & 1) * L.slabC, nJk, s_cc[sk]);
-    if (nIp > 0 && nc > 0) xupdate(row_src(rr - 1, (int)((rr - 1) & 1)), nIp, s_cr[slot(rr - 1)]);
-    if (nIp > 0 && a.y_out) yupdate(rr - 1);
+    if (tid < kHalf) {
+      zupdate(slabC + (size_t)(rr & 1) * L.slabC, nJk, s_cc[sk], tid, kHalf);
+    } else {
+      const int lt = tid - kHalf, nt = T - kHalf;
+      if (nIp > 0 && nc > 0) xupdate(row_src(rr - 1, (int)((rr - 1) & 1)), nIp, s_cr[slot(rr - 1)], lt, nt);
+      if (nIp > 0 && a.y_out) yupdate(rr - 1, lt, nt);
+    }
     __syncthreads();
     // phase B: this workgroup's partial vector: A_{:,J_{k+1}}^T z^k (row groups), A_{I_k,C} x^{k-1}
     // + (z^k - b) on owned rows of I_k, and ||x^{k-1} - x_ref||^2
     unsigned long long* P = gs.part + ((size_t)(rr & 1) * G + w) * E * 2;
     const unsigned ep = epoch + 1;
     const bool has_err = checking && rr >= 2 && ((rr - 1) % ce == 0);
-    if (nJn > 0) push_q(slabC + (size_t)((rr + 1) & 1) * L.slabC, nJn, P, ep);
-    {
+    if (tid < kHalf) {
+      if (nJn > 0) push_q(slabC + (size_t)((rr + 1) & 1) * L.slabC, nJn, P, ep, tid, kHalf);
+    } else {
       const TP* Sr = row_src(rr, (int)(rr & 1));
       const int64_t rI = s_r0[sk];
-      for (int l = tid; l < nIk; l += T) {
+      for (int l = tid - kHalf; l < nIk; l += T - kHalf) {
         double acc = 0.0;
         if constexpr (RowLds) {
 #pragma unroll 4
@@ -609,8 +623,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
         if (gl >= r0 && gl < r1) acc += z[gl - r0] - bl[gl - r0];
         st_tagged(P, MJ + l, acc, ep);
       }
+      if (has_err && tid >= T - 64) err_partial(P, ep);  // wave 3
     }
-    if (has_err) err_partial(P, ep);
     alive = sync_round(++epoch, (int)(rr & 1), nJn, nIk, has_err, rr + 2 <= K ? rr + 2 : 0, (int)(rr & 1),
                        rr + 1 <= K ? rr + 1 : 0, (int)((rr + 1) & 1));
     if (!alive) break;
@@ -635,13 +649,13 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   if (alive && !stopped) {
     // epilogue: x^K from u^K, then the error of x^K
     const int sK = slot(K);
-    if (nc > 0) xupdate(row_src(K, (int)(K & 1)), s_nI[sK], s_cr[sK]);
-    if (a.y_out) yupdate(K);
+    if (nc > 0) xupdate(row_src(K, (int)(K & 1)), s_nI[sK], s_cr[sK], tid, T);
+    if (a.y_out) yupdate(K, tid, T);
     __syncthreads();
     last_k = a.k0 + K;
     if (a.x_ref != nullptr) {
       const int par = (int)((K + 1) & 1);
-      err_partial(gs.part + ((size_t)par * G + w) * E * 2, epoch + 1);
+      if (tid < 64) err_partial(gs.part + ((size_t)par * G + w) * E * 2, epoch + 1);
       alive = sync_round(++epoch, par, 0, 0, true, 0, 0, 0, 0);
       if (alive) {
         last_err2 = s_err2;
