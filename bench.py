@@ -224,6 +224,13 @@ def bench_batched(args):
         bytes_alg += esz * per * float(np.max(its))
         flops += 4.0 * per * float(np.sum(its))
         q += S.B.shape[0]
+    per_system = []
+    q = 0
+    for S in systems:
+        k = S.B.shape[0]
+        per_system.append([int(S.A.shape[0]), int(S.A.shape[1]), getattr(S, "rank", None),
+                           int(np.max(out["tile"][q:q + k])), int(np.max(out["iterations"][q:q + k]))])
+        q += k
     gbs = bytes_alg / (kernel_ms * 1e-3) / 1e9
     tflops = flops / (kernel_ms * 1e-3) / 1e12
     # plain FP64 REBK on the same inputs, one right-hand side at a time (sampled systems)
@@ -268,6 +275,8 @@ def bench_batched(args):
         "speedup_vs_plain_f64_est": plain_total_est / (wall / args.steps),
         "plain_f64_sample": plain,
         "prep_seconds": {"generate": t_gen, "create": t_create, "autotune": t_tune},
+        # per system: rows, columns, rank (null: full), tile width, most iterations of a right-hand side
+        "per_system": per_system,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                      "traffic": None, "kernel": "batch_solve_kernel",
                      "fp64_tflops": tflops, "fp64_peak_tflops": FP64_PEAK_TFLOPS,

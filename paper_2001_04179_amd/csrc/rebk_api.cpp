@@ -615,6 +615,10 @@ struct rebk_batch {
   double* xref2_d = nullptr;
   size_t tasks_cap = 0, iters_cap = 0, status_cap = 0, err2_cap = 0, xref2_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // the tile widths run as separate kernels at the same time: two more streams, forked from and
+  // joined back into `stream` with events
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
 
   ~rebk_batch() {
     dfree(sys_d);
@@ -625,6 +629,11 @@ struct rebk_batch {
     dfree(xref2_d);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (fork) (void)hipEventDestroy(fork);
+    for (int q = 0; q < 2; ++q) {
+      if (join[q]) (void)hipEventDestroy(join[q]);
+      if (side[q]) (void)hipStreamDestroy(side[q]);
+    }
   }
 };
 
@@ -661,7 +670,8 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   if (c.max_tile != 1 && c.max_tile != 2 && c.max_tile != 4) return fail(REBK_ERR_INVALID, "max_tile must be 1, 2 or 4");
   if (c.lds_budget <= 0 || c.lds_budget > kLdsMax) return fail(REBK_ERR_INVALID, "lds_budget out of range");
   const int32_t ns = b->nsys;
-  // tiles: per system the widest tile that fits the LDS budget, remainder in smaller tiles
+  // tiles: per system the widest tile that fits the LDS budget (narrower for the longest systems,
+  // below), remainder in smaller tiles
   struct Tile {
     int32_t sys, rhs0, R;
     int64_t rhs_index;  // global index of the tile's first right-hand side
@@ -670,18 +680,37 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   std::vector<Tile> tiles;
   std::vector<int64_t> rhs_base(ns + 1, 0);
   for (int32_t s = 0; s < ns; ++s) rhs_base[s + 1] = rhs_base[s] + o->nrhs[s];
-  size_t lds_max = 0;
+  // A tile of width R costs about (panel entries per iteration) x (iterations of the previous
+  // solve) x (1 + R / 4): the panel stream is shared by the R right-hand sides, the LDS traffic and
+  // arithmetic grow with R.  Wide tiles cost less in total, but a system whose single tile would
+  // run longer than the average load of a compute unit sets the time of the whole batch: such a
+  // system gets narrower tiles (more of them run at once).
+  std::vector<int> Rsys(ns, 0);
+  double total = 0.0;
   for (int32_t s = 0; s < ns; ++s) {
     const rebk_handle* h = b->hs[s];
-    int Rfit = 0;
     for (int R = c.max_tile; R >= 1; R >>= 1)
       if (rebk::batch_lds_bytes(h->m, h->n, R, b->max_nJ, b->max_nI, c.threads) <= (size_t)c.lds_budget) {
-        Rfit = R;
+        Rsys[s] = R;
         break;
       }
-    if (Rfit == 0)
+    if (Rsys[s] == 0)
       return fail(REBK_ERR_INVALID, "system %d (%lld x %lld) does not fit %d bytes of LDS", s, (long long)h->m,
                   (long long)h->n, c.lds_budget);
+    const double per_iter = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
+    const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
+    total += per_iter * iters * (1.0 + 0.25 * Rsys[s]) * ((o->nrhs[s] + Rsys[s] - 1) / Rsys[s]);
+  }
+  const double per_cu_load = total / (b->cus > 0 ? b->cus : 1);
+  for (int32_t s = 0; s < ns; ++s) {
+    const rebk_handle* h = b->hs[s];
+    const double per_iter = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
+    const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
+    while (Rsys[s] > 1 && per_iter * iters * (1.0 + 0.25 * Rsys[s]) > per_cu_load) Rsys[s] >>= 1;
+  }
+  for (int32_t s = 0; s < ns; ++s) {
+    const rebk_handle* h = b->hs[s];
+    const int Rfit = Rsys[s];
     const double per_iter = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
     const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
     int32_t done = 0;
@@ -689,32 +718,28 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
       int R = Rfit;
       while (R > o->nrhs[s] - done) R >>= 1;
       tiles.push_back({s, done, R, rhs_base[s] + done, per_iter * iters * (1.0 + 0.25 * R)});
-      const size_t lds = rebk::batch_lds_bytes(h->m, h->n, R, b->max_nJ, b->max_nI, c.threads);
-      if (lds > lds_max) lds_max = lds;
       done += R;
     }
   }
-  // order: longest first; with xcd_order, the tiles of a system are cut into groups of at most
-  // one XCD's worth of compute units (so a system with many right-hand sides still spreads over
-  // the chip), groups go to the least loaded of the 8 XCDs, and workgroup 8*slot + x runs slot
-  // `slot` of XCD x
-  std::vector<int32_t> order;  // tile index per workgroup, -1 for an empty slot
-  {
-    std::vector<int32_t> idx(tiles.size());
-    for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int32_t)q;
+  // Order, per tile width (each width is its own kernel): longest first; with xcd_order, the tiles
+  // of a system are cut into groups of at most one XCD's worth of compute units (so a system with
+  // many right-hand sides still spreads over the chip), groups go to the least loaded of the 8
+  // XCDs, and workgroup 8*slot + x of the launch runs slot `slot` of XCD x.
+  auto make_order = [&](const std::vector<int32_t>& idx) -> std::vector<int32_t> {
+    std::vector<int32_t> ord;  // tile index per workgroup, -1 for an empty slot
     if (c.xcd_order) {
       const size_t per_xcd = (size_t)(b->cus >= 8 ? b->cus / 8 : 1);
       std::vector<std::vector<int32_t>> by_sys(ns);
-      for (size_t q = 0; q < tiles.size(); ++q) by_sys[tiles[q].sys].push_back((int32_t)q);
+      for (int32_t q : idx) by_sys[tiles[q].sys].push_back(q);
       std::vector<std::vector<int32_t>> groups;
       std::vector<double> gcost;
-      for (int32_t s = 0; s < ns; ++s)
-        for (size_t q0 = 0; q0 < by_sys[s].size(); q0 += per_xcd) {
+      for (int32_t s_ = 0; s_ < ns; ++s_)
+        for (size_t q0 = 0; q0 < by_sys[s_].size(); q0 += per_xcd) {
           groups.emplace_back();
           double cst = 0.0;
-          for (size_t q = q0; q < by_sys[s].size() && q < q0 + per_xcd; ++q) {
-            groups.back().push_back(by_sys[s][q]);
-            cst += tiles[by_sys[s][q]].cost;
+          for (size_t q = q0; q < by_sys[s_].size() && q < q0 + per_xcd; ++q) {
+            groups.back().push_back(by_sys[s_][q]);
+            cst += tiles[by_sys[s_][q]].cost;
           }
           gcost.push_back(cst);
         }
@@ -732,13 +757,31 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
       }
       size_t slots = 0;
       for (auto& l : lists) slots = l.size() > slots ? l.size() : slots;
-      order.assign(slots * 8, -1);
+      ord.assign(slots * 8, -1);
       for (int x = 0; x < 8; ++x)
-        for (size_t q = 0; q < lists[x].size(); ++q) order[q * 8 + x] = lists[x][q];
+        for (size_t q = 0; q < lists[x].size(); ++q) ord[q * 8 + x] = lists[x][q];
     } else {
-      std::stable_sort(idx.begin(), idx.end(), [&](int32_t p, int32_t q) { return tiles[p].cost > tiles[q].cost; });
-      order = idx;
+      ord = idx;
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t p, int32_t q) { return tiles[p].cost > tiles[q].cost; });
     }
+    return ord;
+  };
+  static constexpr int kWidths[3] = {4, 2, 1};
+  std::vector<int32_t> order;
+  size_t seg_off[3] = {0, 0, 0}, seg_len[3] = {0, 0, 0}, seg_lds[3] = {0, 0, 0};
+  for (int wi = 0; wi < 3; ++wi) {
+    std::vector<int32_t> idx;
+    for (size_t q = 0; q < tiles.size(); ++q)
+      if (tiles[q].R == kWidths[wi]) {
+        idx.push_back((int32_t)q);
+        const rebk_handle* h = b->hs[tiles[q].sys];
+        const size_t lds = rebk::batch_lds_bytes(h->m, h->n, kWidths[wi], b->max_nJ, b->max_nI, c.threads);
+        if (lds > seg_lds[wi]) seg_lds[wi] = lds;
+      }
+    const std::vector<int32_t> ord = make_order(idx);
+    seg_off[wi] = order.size();
+    seg_len[wi] = ord.size();
+    order.insert(order.end(), ord.begin(), ord.end());
   }
   const size_t ntask = order.size();
   if (ntask > (size_t)INT32_MAX) return fail(REBK_ERR_INVALID, "too many tasks");
@@ -772,20 +815,46 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   rebk::BatchArgs a{};
   a.sys = b->sys_d;
   a.tasks = b->tasks_d;
-  a.ntasks = (int32_t)ntask;
   a.max_nJ = b->max_nJ;
   a.max_nI = b->max_nI;
   a.max_iter = o->max_iter;
   a.tol = o->tol;
   a.check_every = o->check_every > 0 ? o->check_every : 16;
   a.z0_from_x0 = o->z0_from_x0 ? 1 : 0;
-  int per_cu = 0;
-  HIP_TRY(rebk::batch_max_blocks(b->panel_dtype, c.threads, lds_max, &per_cu));
-  if (per_cu <= 0) return fail(REBK_ERR_INVALID, "batch kernel cannot run with %zu bytes of LDS and %d threads", lds_max, c.threads);
+  for (int wi = 0; wi < 3; ++wi) {
+    if (seg_len[wi] == 0) continue;
+    int per_cu = 0;
+    HIP_TRY(rebk::batch_max_blocks(b->panel_dtype, c.threads, kWidths[wi], seg_lds[wi], &per_cu));
+    if (per_cu <= 0)
+      return fail(REBK_ERR_INVALID, "batch kernel cannot run with %zu bytes of LDS and %d threads", seg_lds[wi],
+                  c.threads);
+  }
   hipStream_t st = b->stream;
   HIP_TRY(hipMemcpyAsync(b->tasks_d, tasks.data(), ntask * sizeof(rebk::BatchTask), hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(b->ev0, st));
-  HIP_TRY(rebk::launch_batch_solve(a, b->panel_dtype, c.threads, lds_max, st));
+  // the first non-empty width runs on the caller's stream, the others on the side streams, all at
+  // the same time; the caller's stream then waits for them
+  int nside = 0;
+  bool first = true;
+  for (int wi = 0; wi < 3; ++wi) {
+    if (seg_len[wi] == 0) continue;
+    hipStream_t ls = st;
+    if (!first) {
+      if (nside == 0) HIP_TRY(hipEventRecord(b->fork, st));
+      ls = b->side[nside];
+      HIP_TRY(hipStreamWaitEvent(ls, b->fork, 0));
+    }
+    rebk::BatchArgs aw = a;
+    aw.tasks = b->tasks_d + seg_off[wi];
+    aw.ntasks = (int32_t)seg_len[wi];
+    HIP_TRY(rebk::launch_batch_solve(aw, b->panel_dtype, c.threads, kWidths[wi], seg_lds[wi], ls));
+    if (!first) {
+      HIP_TRY(hipEventRecord(b->join[nside], ls));
+      ++nside;
+    }
+    first = false;
+  }
+  for (int q = 0; q < nside; ++q) HIP_TRY(hipStreamWaitEvent(st, b->join[q], 0));
   HIP_TRY(hipEventRecord(b->ev1, st));
   std::vector<int64_t> it(ntask);
   std::vector<int32_t> stt(ntask);
@@ -896,6 +965,11 @@ int rebk_batch_create(rebk_batch_t* out, int32_t nsys, const rebk_handle_t* syst
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e == hipSuccess) e = hipEventCreate(&b->ev0);
   if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+    e = hipEventCreateWithFlags(&b->join[q], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking);
+  }
   if (e != hipSuccess) return bail(fail(REBK_ERR_HIP, "batch setup: %s", hipGetErrorString(e)));
   *out = b;
   return REBK_OK;

@@ -106,10 +106,10 @@ __device__ __forceinline__ int pow2_at_least(int x) {
 }
 
 constexpr int kDrawBatch = 64;  // block draws computed at a time
-// panel loads a thread issues before it consumes them: more for narrow tiles, whose accumulators
-// leave registers free
+// panel loads a thread issues before it consumes them (one entry each): a task's passes over a
+// panel are chains of such groups, so the number in flight sets the streaming rate of the CU
 template <int R>
-constexpr int unroll_for() { return R >= 8 ? 2 : (R >= 4 ? 4 : 8); }
+constexpr int unroll_for() { return R >= 4 ? 16 : 8; }
 // 4-entry vector loads in flight: phases whose accumulators are R values per lane, and phases
 // that keep 4 R accumulators (four rows at once)
 template <int R>
@@ -634,20 +634,17 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
   }
 }
 
-template <typename TP>
-__global__ void __launch_bounds__(512) batch_solve_kernel(BatchArgs a) {
+// One kernel per tile width R (every task of a launch has width R) and per workgroup size: a
+// single kernel holding all three widths needs more registers than a wave has and spills.
+template <typename TP, int R, int kThreads>
+__global__ void __launch_bounds__(kThreads) batch_solve_kernel(BatchArgs a) {
   extern __shared__ double lds[];
   __shared__ int s_j[kDrawBatch], s_i[kDrawBatch];
   if ((int)blockIdx.x >= a.ntasks) return;
   const BatchTask tk = a.tasks[blockIdx.x];
-  if (tk.sys < 0) return;
+  if (tk.sys < 0 || tk.R != R) return;
   const BatchSys S = a.sys[tk.sys];
-  switch (tk.R) {
-    case 1: run_task<TP, 1>(S, tk, a, lds, s_j, s_i); break;
-    case 2: run_task<TP, 2>(S, tk, a, lds, s_j, s_i); break;
-    case 4: run_task<TP, 4>(S, tk, a, lds, s_j, s_i); break;
-    default: break;
-  }
+  run_task<TP, R>(S, tk, a, lds, s_j, s_i);
 }
 
 }  // namespace
@@ -656,25 +653,40 @@ size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int 
   return batch_layout(m, n, R, max_nJ, max_nI, threads).total * sizeof(double);
 }
 
-hipError_t batch_max_blocks(int panel_dtype, int threads, size_t lds_bytes, int* blocks_per_cu) {
+namespace {
+template <typename TP>
+const void* batch_kernel_ptr(int R, int threads) {
+  if (threads <= 256) {
+    return R == 1 ? (const void*)batch_solve_kernel<TP, 1, 256>
+                  : (R == 2 ? (const void*)batch_solve_kernel<TP, 2, 256> : (const void*)batch_solve_kernel<TP, 4, 256>);
+  }
+  return R == 1 ? (const void*)batch_solve_kernel<TP, 1, 512>
+                : (R == 2 ? (const void*)batch_solve_kernel<TP, 2, 512> : (const void*)batch_solve_kernel<TP, 4, 512>);
+}
+}  // namespace
+
+hipError_t batch_max_blocks(int panel_dtype, int threads, int R, size_t lds_bytes, int* blocks_per_cu) {
+  if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
   return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
     using TP = typename decltype(tag)::T;
-    hipError_t e = hipFuncSetAttribute((const void*)batch_solve_kernel<TP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void* k = batch_kernel_ptr<TP>(R, threads);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void*)batch_solve_kernel<TP>, threads,
-                                                        lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, threads, lds_bytes);
   });
 }
 
-hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st) {
+hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, int R, size_t lds_bytes,
+                              hipStream_t st) {
+  if ((threads != 256 && threads != 512) || (R != 1 && R != 2 && R != 4)) return hipErrorInvalidValue;
   return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
     using TP = typename decltype(tag)::T;
-    hipError_t e = hipFuncSetAttribute((const void*)batch_solve_kernel<TP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void* k = batch_kernel_ptr<TP>(R, threads);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_solve_kernel<TP>), dim3(a.ntasks), dim3(threads), lds_bytes, st, a);
-    return hipGetLastError();
+    BatchArgs aa = a;
+    void* args[] = {&aa};
+    return hipLaunchKernel(k, dim3(a.ntasks), dim3(threads), args, lds_bytes, st);
   });
 }
 

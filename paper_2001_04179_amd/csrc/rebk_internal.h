@@ -135,8 +135,10 @@ hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, bool row_lds
 hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, const SolveArgs& a,
                            const double* x, const double* z, double* partials, int nparts, hipStream_t st);
 size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads);
-hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, size_t lds_bytes, hipStream_t st);
-hipError_t batch_max_blocks(int panel_dtype, int threads, size_t lds_bytes, int* blocks_per_cu);
+// One launch runs tasks of one tile width R (1, 2 or 4).
+hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, int R, size_t lds_bytes,
+                              hipStream_t st);
+hipError_t batch_max_blocks(int panel_dtype, int threads, int R, size_t lds_bytes, int* blocks_per_cu);
 // Gram matrix of one block's shorter side: G[a1][a2] = sum_{t < L} X(a1, t) X(a2, t) with
 // X(a, t) = panel[base + a * sa + t * st]; G stored row-major (d x d) at gram offset `gram`.
 struct GramDesc {
