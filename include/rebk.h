@@ -239,7 +239,7 @@ int rebk_solve_refined(rebk_handle_t h, const rebk_refine_opts_t *opts, rebk_res
 
 /* ------------------------------------------------------------------------
  * Batched solves: many independent systems, each with several right-hand
- * sides, in one launch.  Every right-hand side is an exact REBK run
+ * sides, in one call.  Every right-hand side is an exact REBK run
  * (Algorithm 1) with z^0 = b and x^0 = x0 (or 0); the right-hand sides of
  * one system share its block sequence, drawn from the Philox stream of the
  * system's id (the counter's second word), so each panel read serves all
@@ -300,12 +300,17 @@ typedef struct {
 } rebk_batch_rhs_t;
 
 /*
- * Solve every right-hand side of every system of the batch in one launch.
- * Each workgroup takes up to max_tile right-hand sides of one system and
- * keeps their iterates (m + n) x tile in LDS, so each system needs
- * 8 (m + n) bytes plus a little under the LDS budget.  out (host,
- * sum of nrhs entries, system after system) receives per right-hand side
- * results; time_ms (host, may be NULL) the device time of the launch.
+ * Solve every right-hand side of every system of the batch.  Each
+ * workgroup takes up to max_tile right-hand sides of one system and keeps
+ * their iterates (m + n) x tile in LDS, so each system needs 8 (m + n)
+ * bytes plus a little under the LDS budget.  A system's tile width is the
+ * widest that fits, narrowed for systems whose single tile would outlast
+ * the average load of a compute unit in the previous solve.  The tiles of
+ * each width run as one kernel; the kernels of different widths run at
+ * the same time on two library streams forked from and joined back into
+ * the batch's stream.  out (host, sum of nrhs entries, system after
+ * system) receives per right-hand side results; time_ms (host, may be
+ * NULL) the device time from the first launch to the join.
  * Returns REBK_OK when every right-hand side stopped on the tolerance (or
  * no stop rule was given), else REBK_NOT_CONVERGED or REBK_DIVERGED; errors
  * REBK_ERR_INVALID (bad options, a system too large for LDS), REBK_ERR_OOM,
