@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -55,9 +56,10 @@ def parse():
     p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched", "mixed", "sweeps", "warmstart"],
                    help="rank1500: the 20000 x 2000 single system; batched: 256 systems x 16 right-hand sides; "
                         "mixed: the 2000 x 50000 rank-1200 system, BF16/FP16 panels with FP64 refinement")
-    p.add_argument("--ws-train", type=int, default=16384,
-                   help="training right-hand sides (65536 in the full configuration; REBK makes their targets)")
-    p.add_argument("--ws-eval", type=int, default=2048)
+    p.add_argument("--ws-train", type=int, default=65536,
+                   help="training right-hand sides (REBK makes their targets; the full configuration takes "
+                        "about 5 minutes, most of it generating targets)")
+    p.add_argument("--ws-eval", type=int, default=4096)
     p.add_argument("--ws-epochs", type=int, default=60)
     p.add_argument("--ws-gen-iters", type=int, default=0,
                    help="iterations REBK runs to produce the training targets (0: the count that takes the "
@@ -539,11 +541,17 @@ def bench_warmstart(args):
     gen_perm = torch.Generator(device="cpu").manual_seed(11)
     losses = []
     t1 = time.perf_counter()
+    # Adam with a cosine step schedule; the peak rate shrinks with the number of steps (1e-3 up to
+    # 2000 steps): at a constant 1e-3, 15000 steps on the full training set ran into a loss spike
+    total_steps = max(1, args.ws_epochs * nb)
+    lr0, lr_min = 1e-3 * min(1.0, math.sqrt(2000.0 / total_steps)), 1e-5
+    step = 0
     for ep in range(args.ws_epochs):
         perm = torch.randperm(nb * bs, generator=gen_perm).to(A_d.device)
-        lr = 1e-3 if ep < int(0.8 * args.ws_epochs) else 2e-4
         ep_loss = 0.0
         for q in range(nb):
+            lr = lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * step / total_steps))
+            step += 1
             idx = perm[q * bs:(q + 1) * bs]
             ep_loss += net.train_step(Btr[idx].contiguous(), Xtr[idx].contiguous(), lr=lr, b_scale=b_scale)
         losses.append(ep_loss / nb)
