@@ -703,9 +703,10 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   }
   const double per_cu_load = total / (b->cus > 0 ? b->cus : 1);
   for (int32_t s = 0; s < ns; ++s) {
+    if (b->last_iters[s] <= 0) continue;  // no previous solve: nothing to go by
     const rebk_handle* h = b->hs[s];
     const double per_iter = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
-    const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
+    const double iters = (double)b->last_iters[s];
     while (Rsys[s] > 1 && per_iter * iters * (1.0 + 0.25 * Rsys[s]) > per_cu_load) Rsys[s] >>= 1;
   }
   for (int32_t s = 0; s < ns; ++s) {

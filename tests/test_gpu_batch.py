@@ -62,6 +62,23 @@ def test_batch_fixed_iterations_match_oracle(rebk, oracle_lib, threads, max_tile
     close(solvers, batch)
 
 
+def test_batch_narrows_tiles_after_a_solve(rebk, oracle_lib):
+    """The first solve uses the widest tiles that fit (widths 4, 2 and 1 in one call, run as
+    concurrent kernels); the second knows every system's iteration count, and a system whose tile
+    would outlast the average load of a compute unit (7 small systems on a whole chip: the larger
+    ones) gets narrower tiles.  Both match the oracle."""
+    systems = small_batch()
+    solvers, batch = make_batch(rebk, systems)
+    B = [to_dev(S.B) for S in systems]
+    first = batch.solve(B, max_iter=120, threads=512, max_tile=4, xcd_order=1)
+    assert set(np.unique(first["tile"]).tolist()) == {1, 2, 4}
+    oracle_check(oracle_lib, systems, first, first["iterations"])
+    second = batch.solve(B, max_iter=120, threads=512, max_tile=4, xcd_order=1)
+    assert np.all(second["tile"] <= first["tile"]) and np.any(second["tile"] < first["tile"])
+    oracle_check(oracle_lib, systems, second, second["iterations"])
+    close(solvers, batch)
+
+
 def test_batch_stops_on_tolerance(rebk, oracle_lib):
     systems = small_batch(seed=12)
     solvers, batch = make_batch(rebk, systems)
@@ -105,14 +122,19 @@ def test_batch_low_precision_panels(rebk, oracle_lib, panel, stored):
 
 
 def test_batch_order_does_not_change_results(rebk):
+    """Task order alone leaves every result bit-identical (two fresh batches, so both solves use
+    the same tile widths: a later solve may narrow tiles, which sums in another order)."""
     systems = small_batch(seed=14)
     solvers, batch = make_batch(rebk, systems)
+    solvers2, batch2 = make_batch(rebk, systems)
     B = [to_dev(S.B) for S in systems]
     a = batch.solve(B, max_iter=90, xcd_order=1, max_tile=4)
-    b = batch.solve(B, max_iter=90, xcd_order=0, max_tile=4)
+    b = batch2.solve(B, max_iter=90, xcd_order=0, max_tile=4)
+    assert np.array_equal(a["tile"], b["tile"])
     for xa, xb in zip(a["x"], b["x"]):
         assert bool((xa == xb).all())
     close(solvers, batch)
+    close(solvers2, batch2)
 
 
 def test_batch_starting_point_and_sys_ids(rebk, oracle_lib):
