@@ -225,7 +225,7 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   HIP_TRY(rebk::grid_solve_max_blocks(h->panel_dtype, lds, row_lds, &per_cu));
   if (per_cu <= 0 || G > per_cu * h->cus)
     return fail(REBK_ERR_INVALID, "grid of %d workgroups cannot be co-resident (%d per CU)", G, per_cu);
-  if ((h->n + G - 1) / G > rebk::kGridThreads)
+  if ((h->n + G - 1) / G + 8 > rebk::kGridThreads)  // the most columns a workgroup owns
     return fail(REBK_ERR_INVALID, "too many columns per workgroup; use a larger grid");
   if (h->max_nJ > rebk::kGridThreads)
     return fail(REBK_ERR_INVALID, "column blocks wider than %d columns need the one-workgroup kernel", rebk::kGridThreads);

@@ -95,14 +95,25 @@ struct GridLayout {
   size_t slabR;   // panel elements of one row-slab buffer
 };
 
+// Workgroup w of G owns entries [own_lo(w), own_lo(w + 1)) of a dimension of size `total`: the
+// boundaries w * total / G rounded down to a multiple of `al`, so that the panel runs a workgroup
+// copies start on 16-byte boundaries (rows: al = 16 / panel bytes, as column panels have a row
+// stride of a multiple of 16 entries; columns: al = 8, so that the offset c * |I| of a row slab is a
+// multiple of 16 bytes for any block size).  A part holds at most ceil(total / G) + al entries.
+constexpr int kColOwnAlign = 8;
+__host__ __device__ inline int64_t own_lo(int64_t w, int64_t total, int G, int al) {
+  return w >= G ? total : (w * total / G) / al * al;
+}
+
 // row_lds: the row slabs are staged in LDS (else the x-steps read them from the row panels in HBM,
-// for systems whose slabs do not fit).
+// for systems whose slabs do not fit).  esz: bytes per panel entry.
 __host__ __device__ inline GridLayout grid_layout(int64_t m, int64_t n, int max_nI, int max_nJ, int G, int threads,
-                                                  bool row_lds = true) {
+                                                  bool row_lds, int esz) {
   GridLayout L;
-  L.NR = (int)((m + G - 1) / G);
-  L.NC = (int)((n + G - 1) / G);
-  L.dbl = 4 * (size_t)L.NR + 2 * (size_t)L.NC + (size_t)max_nJ + (size_t)max_nI + (size_t)threads + 8;
+  L.NR = (int)((m + G - 1) / G) + 16 / esz;
+  L.NC = (int)((n + G - 1) / G) + kColOwnAlign;
+  // an even count of doubles keeps the slab buffers after them 16-byte aligned
+  L.dbl = (4 * (size_t)L.NR + 2 * (size_t)L.NC + (size_t)max_nJ + (size_t)max_nI + (size_t)threads + 8 + 1) & ~(size_t)1;
   // slab buffers padded to 8 entries, so every buffer starts 16-byte aligned in LDS
   L.slabC = ((size_t)L.NR * max_nJ + 7) / 8 * 8;
   L.slabR = row_lds ? ((size_t)L.NC * max_nI + 7) / 8 * 8 : 0;
@@ -157,22 +168,32 @@ __device__ __forceinline__ bool dma_ok(const TP* src, int64_t stride, int runs, 
   return (((uintptr_t)src | (uintptr_t)dst) & 3) == 0 && (len & 1) == 0 && (runs == 1 || (stride & 1) == 0);
 }
 
-// Copy those runs into LDS.  Waves 1..3 issue global_load_lds copies of 256-byte pieces (one
-// dword per lane), the pieces of all runs spread over the three waves; the copies are
-// asynchronous and complete for the issuing wave after s_waitcnt vmcnt(0).
+// Copy those runs into LDS.  Waves 1..3 issue global_load_lds copies, the pieces of all runs spread
+// over the three waves: 1-KB pieces (16 bytes per lane) when every run starts and ends on 16-byte
+// boundaries at both ends, else 256-byte pieces (one dword per lane).  Lane l of a copy lands at
+// the copy's LDS address + l x (bytes per lane).  The copies are asynchronous and complete for
+// the issuing wave after s_waitcnt vmcnt(0).
 template <typename TP>
 __device__ __forceinline__ void dma_runs(const TP* src, int64_t stride, int runs, int len, TP* dst) {
   const int wave = (int)(threadIdx.x >> 6) - 1, lane = (int)(threadIdx.x & 63);
   const int bytes = len * (int)sizeof(TP);
-  const int pieces = (bytes + 255) / 256;
+  const bool wide = ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) && (bytes & 15) == 0 &&
+                    (runs <= 1 || ((stride * (int64_t)sizeof(TP)) & 15) == 0);
+  const int per_lane = wide ? 16 : 4, piece = 64 * per_lane;
+  const int pieces = (bytes + piece - 1) / piece;
   const int total = runs * pieces;
   for (int p = wave; p < total; p += 3) {
-    const int r = p / pieces, off = (p - r * pieces) * 256;
+    const int r = p / pieces, off = (p - r * pieces) * piece;
     const char* s = (const char*)(src + (int64_t)r * stride);
     char* d = (char*)(dst + (size_t)r * len);
-    if (off + lane * 4 < bytes)
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off + lane * 4),
-                                       (__attribute__((address_space(3))) void*)(d + off), 4, 0, 0);
+    if (off + lane * per_lane < bytes) {
+      if (wide)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off + lane * 16),
+                                         (__attribute__((address_space(3))) void*)(d + off), 16, 0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(s + off + lane * 4),
+                                         (__attribute__((address_space(3))) void*)(d + off), 4, 0, 0);
+    }
   }
 }
 
@@ -189,9 +210,10 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
   const int64_t m = a.m, n = a.n;
   const int MJ = a.max_nJ, MI = a.max_nI;
-  const GridLayout L = grid_layout(m, n, MI, MJ, G, T, RowLds);
-  const int64_t r0 = (int64_t)w * m / G, r1 = (int64_t)(w + 1) * m / G;
-  const int64_t cA = (int64_t)w * n / G, cB = (int64_t)(w + 1) * n / G;
+  const GridLayout L = grid_layout(m, n, MI, MJ, G, T, RowLds, (int)sizeof(TP));
+  const int ra = 16 / (int)sizeof(TP);
+  const int64_t r0 = own_lo(w, m, G, ra), r1 = own_lo(w + 1, m, G, ra);
+  const int64_t cA = own_lo(w, n, G, kColOwnAlign), cB = own_lo(w + 1, n, G, kColOwnAlign);
   const int nr = (int)(r1 - r0), nc = (int)(cB - cA);
 
   double* z = lds;          // z on owned rows
@@ -693,8 +715,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 }  // namespace
 
 size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype, bool row_lds) {
-  const GridLayout L = grid_layout(a.m, a.n, a.max_nI, a.max_nJ, grid, kGridThreads, row_lds);
   const size_t esz = panel_dtype == 0 ? 8 : (panel_dtype == 1 ? 4 : 2);
+  const GridLayout L = grid_layout(a.m, a.n, a.max_nI, a.max_nJ, grid, kGridThreads, row_lds, (int)esz);
   return L.dbl * sizeof(double) + 2 * (L.slabC + L.slabR) * esz + 64;
 }
 
