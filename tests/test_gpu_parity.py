@@ -44,6 +44,19 @@ def test_grid_sizes(rebk, oracle_lib, cfg1, grid_wgs):
     gpu_vs_oracle(rebk, oracle_lib, cfg1, kernel="grid", grid_wgs=grid_wgs, max_iter=300)
 
 
+@pytest.mark.parametrize("panel", ["f32", "bf16"])
+@pytest.mark.parametrize("grid_wgs", [9, 64, 256])
+def test_grid_sizes_low_precision_panels(rebk, oracle_lib, panel, grid_wgs):
+    """Workgroup ranges start on 16-byte boundaries of the panels (multiples of 4 rows for FP32,
+    8 for 2-byte panels, and of 8 columns): with many workgroups on a ragged system some own no
+    rows or no columns, and the slab copies mix 16-byte and 4-byte pieces."""
+    S = W.type2(517, 203, rng_seed=21, noise=0.2, row_tau=50, col_tau=16, alpha_c=1.0, seed=5)
+    rnd = {"f32": W.round_to_f32, "bf16": W.round_to_bf16}[panel]
+    print(f"case ragged 517x203 panel={panel} grid_wgs={grid_wgs}", flush=True)
+    gpu_vs_oracle(rebk, oracle_lib, S, kernel="grid", grid_wgs=grid_wgs, max_iter=200, panel=panel,
+                  A_stored=rnd(S.A))
+
+
 def test_grid_too_small_is_rejected(rebk, cfg1):
     """One workgroup cannot hold the whole 1000 x 100 iterate plus its slabs in LDS."""
     S = cfg1
