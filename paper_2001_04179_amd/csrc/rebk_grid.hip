@@ -39,8 +39,9 @@ using namespace dev;
 
 constexpr unsigned kSpinLimit = 1u << 22;  // polls before a barrier gives up (seconds)
 // Entries per reduction chunk (1, 2, 4 or 8).  Smaller chunks mean more owners, each polling fewer
-// bytes per round; on the 20000 x 2000 workload 2 was fastest (8: +13%, 4: +6%, 1: +2% per iteration).
-constexpr int kChunk = 2;
+// bytes per round; on the 20000 x 2000 workload 1 is fastest (2: +4%, 4: +3%, 8: +13% per
+// iteration).
+constexpr int kChunk = 1;
 static_assert(kChunk == 1 || kChunk == 2 || kChunk == 4 || kChunk == 8, "chunk of 1, 2, 4 or 8 entries");
 constexpr int kCopies = kGridSumCopies;     // copies of the reduced vector
 
