@@ -51,7 +51,8 @@ def parse():
     p.add_argument("--grid-wgs", type=int, default=0)
     p.add_argument("--panels", default="f64,f32")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-iters", type=int, default=2000)
+    p.add_argument("--cpu-sample-iters", type=int, default=12000,
+                   help="oracle iterations timed for the CPU baseline (about 11 s on one core)")
     p.add_argument("--scale", type=int, default=1, help="divide the problem dimensions (quick checks only)")
     p.add_argument("--workload", default="rank1500", choices=["rank1500", "batched", "mixed", "sweeps", "warmstart"],
                    help="rank1500: the 20000 x 2000 single system; batched: 256 systems x 16 right-hand sides; "
