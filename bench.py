@@ -10,7 +10,7 @@ plus rebk_solve_ex to the tolerance, inputs resident in HBM.  Both panel precisi
 (FP64 panels, the plain method; FP32 panels with FP64 iterates); the faster one that reaches the
 tolerance is the reported form.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the program runs on one GPU.
 """
 from __future__ import annotations
 
@@ -607,7 +607,7 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this program runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)

@@ -351,8 +351,8 @@ int rebk_block_betas(rebk_handle_t h, int32_t max_steps, double rtol, double *be
  * Learned warm start.  A network maps a right-hand side b to y; the start
  * x0 = A^T y lies in range(A^T) and z0 = b - A x0 in b + range(A), the
  * hypotheses of Theorem 7, so REBK from (x0, z0) still converges to A^+ b
- * (plain REBK from x0 = 0, z0 = b is the fallback and the judge of its
- * error).  The network is
+ * (plain REBK from x0 = 0, z0 = b is the fallback, taken where
+ * ||b - A x0|| >= ||b||).  The network is
  *   h1 = relu(W1 (s b) + c1),  h2 = relu(W2 h1 + c2),  y = W3 h2 + c3,
  *   x0 = out_scale A^T y
  * (s: a scale of the input), trained with Adam (Kingma and Ba) on

@@ -4,7 +4,7 @@
  * A plain, slow, FP64 CPU implementation of the randomized extended block
  * Kaczmarz method (REBK) of Du, Si and Sun, "Randomized extended block
  * Kaczmarz for solving least squares" (arXiv:2001.04179), Section 2,
- * Algorithm 1.  It is the parity judge for the GPU library: only the test
+ * Algorithm 1.  It is the parity reference for the GPU library: only the test
  * suite, the smoke check and the CPU-baseline leg of the benchmark may load
  * it.  It shares no code, header, table or helper with the GPU library.
  *
