@@ -91,6 +91,23 @@ def test_rek_special_case(rebk, oracle_lib, kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("shape,taus", [((1, 37), (1, 5)), ((53, 1), (7, 1)), ((2, 2), (1, 1))])
+def test_degenerate_shapes(rebk, oracle_lib, kernel, shape, taus):
+    """One row, one column, 2 x 2 with single-entry blocks: on the whole-chip kernel all but one
+    workgroup own no rows or no columns."""
+    m, n = shape
+    A = np.random.default_rng(31).standard_normal((m, n))
+    row_off = list(range(0, m, taus[0])) + [m]
+    col_off = list(range(0, n, taus[1])) + [n]
+    S = W.general(A, rng_seed=32, noise=0.1, row_off=row_off, col_off=col_off, seed=2)
+    print(f"case degenerate {m}x{n} kernel={kernel}", flush=True)
+    out, ref = gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=150)
+    # and the iterates approach A^+ b
+    xp = np.linalg.pinv(A) @ S.b
+    assert np.linalg.norm(ref["x"] - xp) < 0.5 * np.linalg.norm(xp)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 def test_single_blocks(rebk, oracle_lib, kernel):
     """s = t = 1: the sampler always draws the whole matrix."""
     A = np.random.default_rng(13).standard_normal((90, 40))
