@@ -279,7 +279,7 @@ typedef struct {
                                        first check where every one of them has
                                        ||x - x_ref|| / ||x_ref|| < tol; <= 0: run max_iter */
     int64_t check_every;            /* check interval (0 means 16) */
-    int32_t threads;                /* threads per workgroup: 256 or 512 (0: tuned, else 512) */
+    int32_t threads;                /* threads per workgroup: 256, 512 or 1024 (0: tuned, else 512) */
     int32_t lds_budget;             /* LDS bytes per workgroup for the iterates (0: tuned, else
                                        the largest that fits) */
     int32_t max_tile;               /* most right-hand sides per workgroup: 1, 2 or 4

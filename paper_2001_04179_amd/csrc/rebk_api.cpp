@@ -666,7 +666,8 @@ int grow(T*& p, size_t& cap, size_t need) {
 // Run the batch once with configuration c.  Fills out (may be NULL) and *ms.
 int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, rebk_batch_rhs_t* out, double* ms,
               int* overall) {
-  if (c.threads != 256 && c.threads != 512) return fail(REBK_ERR_INVALID, "threads must be 256 or 512");
+  if (c.threads != 256 && c.threads != 512 && c.threads != 1024)
+    return fail(REBK_ERR_INVALID, "threads must be 256, 512 or 1024");
   if (c.max_tile != 1 && c.max_tile != 2 && c.max_tile != 4) return fail(REBK_ERR_INVALID, "max_tile must be 1, 2 or 4");
   if (c.lds_budget <= 0 || c.lds_budget > kLdsMax) return fail(REBK_ERR_INVALID, "lds_budget out of range");
   const int32_t ns = b->nsys;
@@ -1005,7 +1006,7 @@ int rebk_batch_autotune(rebk_batch_t b, const rebk_batch_opts_t* o, int64_t prob
   rebk_batch_opts_t p = *o;
   p.max_iter = probe_iters;
   p.tol = 0.0;
-  const int cand_threads[] = {256, 512};
+  const int cand_threads[] = {256, 512, 1024};
   const int cand_tile[] = {1, 2, 4};
   const int cand_lds[] = {kLdsMax, 80 * 1024 - 512};
   BatchConfig best{0, 0, 0, 1};

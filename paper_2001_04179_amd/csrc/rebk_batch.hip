@@ -107,15 +107,16 @@ __device__ __forceinline__ int pow2_at_least(int x) {
 
 constexpr int kDrawBatch = 64;  // block draws computed at a time
 // panel loads a thread issues before it consumes them (one entry each): a task's passes over a
-// panel are chains of such groups, so the number in flight sets the streaming rate of the CU
-template <int R>
-constexpr int unroll_for() { return R >= 4 ? 16 : 8; }
+// panel are chains of such groups, so the number in flight sets the streaming rate of the CU.
+// With 1024 threads a wave has half the registers (and the CU twice the threads): half as many.
+template <int R, int kThreads>
+constexpr int unroll_for() { return (R >= 4 ? 16 : 8) / (kThreads >= 1024 ? 2 : 1); }
 // 4-entry vector loads in flight: phases whose accumulators are R values per lane, and phases
 // that keep 4 R accumulators (four rows at once)
-template <int R>
-constexpr int vec_unroll_light() { return R >= 2 ? 8 : 16; }
-template <int R>
-constexpr int vec_unroll_heavy() { return R >= 2 ? 4 : 8; }
+template <int R, int kThreads>
+constexpr int vec_unroll_light() { return (R >= 2 ? 8 : 16) / (kThreads >= 1024 ? 2 : 1); }
+template <int R, int kThreads>
+constexpr int vec_unroll_heavy() { return (R >= 2 ? 4 : 8) / (kThreads >= 1024 ? 2 : 1); }
 
 struct BatchLayout {
   size_t z, x, v, u, ew, total;  // offsets in doubles
@@ -133,7 +134,7 @@ __host__ __device__ inline BatchLayout batch_layout(int64_t m, int64_t n, int R,
   return L;
 }
 
-template <typename TP, int R>
+template <typename TP, int R, int kThreads>
 __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs& a, double* lds, int* s_j,
                          int* s_i) {
   const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = (T + 63) >> 6;
@@ -155,7 +156,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
   const GLOBAL_AS double* __restrict__ coef_row = gptr(S.coef_row);
   const GLOBAL_AS double* __restrict__ bvec = gptr(tk.b);
   const GLOBAL_AS double* __restrict__ xref = gptr(tk.x_ref);
-  constexpr int kUnroll = unroll_for<R>();
+  constexpr int kUnroll = unroll_for<R, kThreads>();
 
   for (int64_t e = tid; e < (int64_t)R * m; e += T) z[e] = bvec[e];
   if (tk.x_in) {
@@ -344,7 +345,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     } else {
     const int64_t nq = (m + 3) >> 2;
       {
-        constexpr int U = vec_unroll_light<R>();
+        constexpr int U = vec_unroll_light<R, kThreads>();
         int G = T / pow2_at_least(nJ);
         if (G > 64) G = 64;
         if (G < 1) G = 1;
@@ -389,7 +390,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
       __syncthreads();
       // ---- z update: Z -= coef_J * A_{:,J} V, one thread per 4-row chunk
       {
-        constexpr int U = vec_unroll_heavy<R>();
+        constexpr int U = vec_unroll_heavy<R, kThreads>();
         const double cc = coef_col[j];
         for (int64_t qq = tid; qq < nq; qq += T) {
           double acc[4][R];
@@ -436,7 +437,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     const bool vrow = R <= 2 && (nI & 3) == 0 && ((n * r0) & 3) == 0;
     const int nqI = nI >> 2;
     if (vrow) {
-      constexpr int U = vec_unroll_heavy<R>();
+      constexpr int U = vec_unroll_heavy<R, kThreads>();
       int G = T / pow2_at_least(nqI);
       if (G > 64) G = 64;
       if (G < 1) G = 1;
@@ -524,7 +525,7 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
     // ---- x update: X -= coef_I * A_{I,:}^T U
     if (vrow) {
       // W lanes per column, one 4-row chunk each; every thread handles U columns at once
-      constexpr int U = vec_unroll_light<R>();
+      constexpr int U = vec_unroll_light<R, kThreads>();
       const double cr = coef_row[i];
       int W = pow2_at_least(nqI);
       if (W > 64) W = 64;
@@ -634,8 +635,9 @@ __device__ void run_task(const BatchSys& S, const BatchTask& tk, const BatchArgs
   }
 }
 
-// One kernel per tile width R (every task of a launch has width R) and per workgroup size: a
-// single kernel holding all three widths needs more registers than a wave has and spills.
+// One kernel per tile width R (every task of a launch has width R) and per workgroup size (256,
+// 512 or 1024 threads): a single kernel holding all three widths needs more registers than a
+// wave has and spills.
 template <typename TP, int R, int kThreads>
 __global__ void __launch_bounds__(kThreads) batch_solve_kernel(BatchArgs a) {
   extern __shared__ double lds[];
@@ -644,7 +646,7 @@ __global__ void __launch_bounds__(kThreads) batch_solve_kernel(BatchArgs a) {
   const BatchTask tk = a.tasks[blockIdx.x];
   if (tk.sys < 0 || tk.R != R) return;
   const BatchSys S = a.sys[tk.sys];
-  run_task<TP, R>(S, tk, a, lds, s_j, s_i);
+  run_task<TP, R, kThreads>(S, tk, a, lds, s_j, s_i);
 }
 
 }  // namespace
@@ -656,6 +658,10 @@ size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int 
 namespace {
 template <typename TP>
 const void* batch_kernel_ptr(int R, int threads) {
+  if (threads > 512) {
+    return R == 1 ? (const void*)batch_solve_kernel<TP, 1, 1024>
+                  : (R == 2 ? (const void*)batch_solve_kernel<TP, 2, 1024> : (const void*)batch_solve_kernel<TP, 4, 1024>);
+  }
   if (threads <= 256) {
     return R == 1 ? (const void*)batch_solve_kernel<TP, 1, 256>
                   : (R == 2 ? (const void*)batch_solve_kernel<TP, 2, 256> : (const void*)batch_solve_kernel<TP, 4, 256>);
@@ -678,7 +684,7 @@ hipError_t batch_max_blocks(int panel_dtype, int threads, int R, size_t lds_byte
 
 hipError_t launch_batch_solve(const BatchArgs& a, int panel_dtype, int threads, int R, size_t lds_bytes,
                               hipStream_t st) {
-  if ((threads != 256 && threads != 512) || (R != 1 && R != 2 && R != 4)) return hipErrorInvalidValue;
+  if ((threads != 256 && threads != 512 && threads != 1024) || (R != 1 && R != 2 && R != 4)) return hipErrorInvalidValue;
   return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
     using TP = typename decltype(tag)::T;
     const void* k = batch_kernel_ptr<TP>(R, threads);
