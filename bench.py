@@ -501,6 +501,9 @@ def bench_warmstart(args):
     Bev, Xev = P["B_eval"], P["X_eval_ref"]
 
     cap = [2_000_000]
+    # one autotuner pass; cold, warm and target solves all use its choice
+    tuned = batch.autotune([Bev], x_ref=[Xev], probe_iters=32)
+    print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
 
     def solve_eval(x0=None):
         torch.cuda.synchronize()
@@ -580,7 +583,7 @@ def bench_warmstart(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"learned warm start: A = U V ({m} x {n}, rank {P['rank']}), {Btr.shape[0]} training / "
                                f"{N} held-out right-hand sides, network {m}-512-512-{m}, tol {tol:g}",
-                   "panel_dtype": "f32", "epochs": args.ws_epochs, "batch": bs},
+                   "panel_dtype": "f32", "epochs": args.ws_epochs, "batch": bs, "tuned": tuned},
         "warm": {"seconds": t_warm, "inference_seconds": t_infer, "iterations_mean": float(warm["iterations"].mean()),
                  "iterations_median": float(np.median(warm["iterations"])), "status": warm["status"],
                  "rel_err_max": float(warm["rel_err"].max())},
