@@ -81,7 +81,9 @@ typedef enum {
 typedef enum {
     REBK_KERNEL_AUTO = 0,     /* WORKGROUP for tiny systems (m |J| + |I| n + 4 (m + n) <= 8192), GRID otherwise */
     REBK_KERNEL_WORKGROUP = 1,/* one workgroup runs the whole solve (small systems) */
-    REBK_KERNEL_GRID = 2      /* one persistent cooperative grid, one grid barrier per iteration */
+    REBK_KERNEL_GRID = 2      /* one persistent cooperative grid, one grid-wide reduction per
+                                 iteration; needs ceil(n / grid) + 8 <= 256 owned columns, blocks
+                                 of at most 256 columns and its slabs within 160 KB of LDS */
 } rebk_kernel_t;
 
 typedef struct {
