@@ -74,7 +74,7 @@ typedef enum {
     REBK_ERR_INVALID = -1,    /* bad argument; nothing was written */
     REBK_ERR_HIP = -2,        /* a HIP runtime call failed */
     REBK_ERR_OOM = -3,        /* device allocation failed */
-    REBK_ERR_TIMEOUT = -4     /* a grid barrier of the persistent kernel exceeded its spin limit */
+    REBK_ERR_TIMEOUT = -4     /* a wait of a persistent kernel (grid or team) exceeded its spin limit */
 } rebk_status_t;
 
 /* Which kernel runs the iterations. */
@@ -291,6 +291,9 @@ typedef struct {
     int32_t z0_from_x0;             /* 1: where x0 is given, start from z0 = b - A x0 (computed from
                                        the stored panels) instead of z0 = b; a right-hand side
                                        whose ||b - A x0|| >= ||b|| falls back to x0 = 0, z0 = b */
+    int32_t team;                   /* teams of workgroups (below): 0 automatic, -1 never, P > 0
+                                       every system in teams of P workgroups (P <= 256; not with
+                                       z0_from_x0) */
 } rebk_batch_opts_t;
 
 /* Result of one right-hand side of a batch. */
@@ -299,6 +302,7 @@ typedef struct {
     double rel_err;      /* ||x - x_ref|| / ||x_ref|| at the last check, or -1 */
     int32_t status;      /* REBK_OK, REBK_NOT_CONVERGED or REBK_DIVERGED */
     int32_t tile;        /* right-hand sides solved together with this one */
+    int32_t team;        /* workgroups that solved them together (0: one workgroup) */
 } rebk_batch_rhs_t;
 
 /*
@@ -310,13 +314,24 @@ typedef struct {
  * the average load of a compute unit in the previous solve.  The tiles of
  * each width run as one kernel; the kernels of different widths run at
  * the same time on two library streams forked from and joined back into
- * the batch's stream.  out (host, sum of nrhs entries, system after
+ * the batch's stream.
+ * Teams: a system whose narrowest tile alone would still outlast the average
+ * load of a compute unit in the previous solve (and whose iteration reads
+ * enough panel to gain from more compute units) is solved by teams instead:
+ * tiles of up to 16 right-hand sides, each split over P workgroups that own
+ * slices of its rows and columns and combine their block products through a
+ * reduction in device memory every iteration.  All teams run in one
+ * cooperative launch on the batch's stream before the other tiles, sharing
+ * the compute units in proportion to their work.  Teams keep the iteration
+ * and stop rule of the other tiles, with the products summed in another
+ * order.  Not used with z0_from_x0.  out (host, sum of nrhs entries, system after
  * system) receives per right-hand side results; time_ms (host, may be
  * NULL) the device time from the first launch to the join.
  * Returns REBK_OK when every right-hand side stopped on the tolerance (or
  * no stop rule was given), else REBK_NOT_CONVERGED or REBK_DIVERGED; errors
- * REBK_ERR_INVALID (bad options, a system too large for LDS), REBK_ERR_OOM,
- * REBK_ERR_HIP.  Synchronizes the stream.
+ * REBK_ERR_INVALID (bad options, a system too large for LDS, forced teams
+ * that do not fit the device), REBK_ERR_OOM, REBK_ERR_HIP, REBK_ERR_TIMEOUT
+ * (a team's reduction exceeded its spin limit).  Synchronizes the stream.
  */
 int rebk_batch_solve(rebk_batch_t b, const rebk_batch_opts_t *opts, rebk_batch_rhs_t *out,
                      double *time_ms);

@@ -268,7 +268,7 @@ class Batch:
             pass
 
     def _opts(self, B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget, max_tile,
-              xcd_order, z0_from_x0=False):
+              xcd_order, z0_from_x0=False, team=0):
         """B[s]: (nrhs_s, m_s) float64 CUDA tensors; x_ref / x0 (optional) and x_out: (nrhs_s, n_s)."""
         if len(B) != self.nsys:
             raise ValueError("one right-hand-side matrix per system")
@@ -307,20 +307,22 @@ class Batch:
         o.max_tile = int(max_tile)
         o.xcd_order = int(xcd_order)
         o.z0_from_x0 = 1 if z0_from_x0 else 0
+        o.team = int(team)
         return o, nrhs, keep
 
     def solve(self, B, *, x_ref=None, x0=None, max_iter: int = 100000, tol: float = 0.0, check_every: int = 0,
               threads: int = 0, lds_budget: int = 0, max_tile: int = 0, xcd_order: int = -1, want_z: bool = False,
-              z0_from_x0: bool = False):
-        """``rebk_batch_solve``.  Returns dict(x=[...], z=[...] or None, iterations, rel_err, status, tile
-        (numpy arrays over all right-hand sides, system after system), time_ms, code)."""
+              z0_from_x0: bool = False, team: int = 0):
+        """``rebk_batch_solve``.  Returns dict(x=[...], z=[...] or None, iterations, rel_err, status, tile,
+        team (numpy arrays over all right-hand sides, system after system), time_ms, code).  team: 0
+        automatic, -1 never, P > 0 every system in teams of P workgroups."""
         dev = self.solvers[0].device
         x_out = [torch.empty((int(b.shape[0]), sv.n), dtype=torch.float64, device=dev)
                  for b, sv in zip(B, self.solvers)]
         z_out = ([torch.empty((int(b.shape[0]), sv.m), dtype=torch.float64, device=dev)
                   for b, sv in zip(B, self.solvers)] if want_z else None)
         o, nrhs, keep = self._opts(B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget,
-                                   max_tile, xcd_order, z0_from_x0)
+                                   max_tile, xcd_order, z0_from_x0, team)
         total = sum(nrhs)
         res = (N.BatchRhs * total)()
         ms = ctypes.c_double(0.0)
@@ -335,6 +337,7 @@ class Batch:
             "rel_err": np.array([r.rel_err for r in res]),
             "rhs_status": np.array([r.status for r in res], dtype=np.int32),
             "tile": np.array([r.tile for r in res], dtype=np.int32),
+            "team": np.array([r.team for r in res], dtype=np.int32),
         }
 
     def autotune(self, B, *, x_ref=None, probe_iters: int = 64):

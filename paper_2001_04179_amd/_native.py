@@ -52,12 +52,12 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [
         ("nrhs", P), ("b_dev", P), ("x0_dev", P), ("x_ref_dev", P), ("x_out_dev", P), ("z_out_dev", P),
         ("max_iter", I64), ("tol", F64), ("check_every", I64), ("threads", I32), ("lds_budget", I32),
-        ("max_tile", I32), ("xcd_order", I32), ("z0_from_x0", I32),
+        ("max_tile", I32), ("xcd_order", I32), ("z0_from_x0", I32), ("team", I32),
     ]
 
 
 class BatchRhs(ctypes.Structure):
-    _fields_ = [("iterations", I64), ("rel_err", F64), ("status", I32), ("tile", I32)]
+    _fields_ = [("iterations", I64), ("rel_err", F64), ("status", I32), ("tile", I32), ("team", I32)]
 
 
 # name -> (restype, argtypes); every function declared in include/rebk.h

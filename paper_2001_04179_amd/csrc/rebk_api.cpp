@@ -13,6 +13,7 @@
 
 #include "rebk.h"
 #include "rebk_internal.h"
+#include "rebk_team.h"
 
 namespace {
 
@@ -604,6 +605,7 @@ struct rebk_batch {
   int32_t max_nJ = 0, max_nI = 0;
   std::vector<rebk_handle*> hs;
   std::vector<int64_t> last_iters;  // per system, from the previous solve (longest-first order)
+  std::vector<int> team_P;          // per system: workgroups per team tile of this solve (0: none)
   rebk::BatchSys* sys_d = nullptr;
   // choices of rebk_batch_autotune (0 / -1: not tuned)
   int32_t tuned_threads = 0, tuned_lds = 0, tuned_tile = 0, tuned_xcd = -1;
@@ -614,6 +616,11 @@ struct rebk_batch {
   double* err2_d = nullptr;
   double* xref2_d = nullptr;
   size_t tasks_cap = 0, iters_cap = 0, status_cap = 0, err2_cap = 0, xref2_cap = 0;
+  // teams: their table, the team of every workgroup of the launch, the reduction words
+  rebk::TeamTask* teams_d = nullptr;
+  int32_t* team_of_wg_d = nullptr;
+  unsigned long long* tsync_d = nullptr;
+  size_t teams_cap = 0, twg_cap = 0, tsync_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // the tile widths run as separate kernels at the same time: two more streams, forked from and
   // joined back into `stream` with events
@@ -627,6 +634,9 @@ struct rebk_batch {
     dfree(status_d);
     dfree(err2_d);
     dfree(xref2_d);
+    dfree(teams_d);
+    dfree(team_of_wg_d);
+    dfree(tsync_d);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (fork) (void)hipEventDestroy(fork);
@@ -663,6 +673,106 @@ int grow(T*& p, size_t& cap, size_t need) {
   return REBK_OK;
 }
 
+// Teams (rebk_batch_solve): sets b->team_P[s], the workgroups of each team tile of system s (0:
+// ordinary tiles), and removes the team systems' cost from *total, the summed tile cost of the
+// batch (in the units of batch_run: panel entries per iteration x iterations x (1 + R / 4)).
+constexpr int kTeamMaxWgs = 256;
+constexpr int kTeamLdsMax = 152 * 1024;  // dynamic LDS of a team workgroup (the kernel has ~6 KB static)
+// A team pays off when a single compute unit's iteration (its panel stream at about 33 GB/s)
+// takes at least twice a team's iteration (about 25 us: slab copies, four block products on the
+// matrix cores and the two reduction hops).
+constexpr double kCuBytesPerSec = 33e9;
+constexpr double kTeamIterSec = 25e-6;
+
+int plan_teams(rebk_batch* b, const rebk_batch_opts_t* o, const std::vector<int>& Rsys, double* total) {
+  const int32_t ns = b->nsys;
+  b->team_P.assign(ns, 0);
+  if (o->team < 0) return REBK_OK;
+  const int cus = b->cus > 0 ? b->cus : 1;
+  auto min_P = [&](int32_t s) -> int {  // smallest team whose workgroups fit the LDS
+    const rebk_handle* h = b->hs[s];
+    for (int P = 2; P <= kTeamMaxWgs; ++P)
+      if (rebk::team_lds_bytes(h->m, h->n, P, b->max_nJ, b->max_nI, b->panel_dtype) <= (size_t)kTeamLdsMax) return P;
+    return 0;
+  };
+  auto team_tiles = [&](int32_t s) { return (o->nrhs[s] + rebk::kTeamR - 1) / rebk::kTeamR; };
+  if (o->team > 0) {
+    if (o->team > kTeamMaxWgs) return fail(REBK_ERR_INVALID, "team must be at most %d workgroups", kTeamMaxWgs);
+    if (o->z0_from_x0) return fail(REBK_ERR_INVALID, "teams do not take z0_from_x0");
+    for (int32_t s = 0; s < ns; ++s) {
+      const int pm = min_P(s);
+      if (pm == 0 || pm > o->team)
+        return fail(REBK_ERR_INVALID, "system %d needs teams of %s %d workgroups", s, pm ? "at least" : "more than",
+                    pm ? pm : kTeamMaxWgs);
+      b->team_P[s] = o->team;
+    }
+    *total = 0.0;
+    return REBK_OK;
+  }
+  if (o->z0_from_x0) return REBK_OK;
+  const double esz = b->panel_dtype == 0 ? 8.0 : (b->panel_dtype == 1 ? 4.0 : 2.0);
+  std::vector<double> load(ns), single(ns), work(ns), per_iter(ns);
+  for (int32_t s = 0; s < ns; ++s) {
+    const rebk_handle* h = b->hs[s];
+    per_iter[s] = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
+    const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
+    load[s] = per_iter[s] * iters * (1.0 + 0.25 * Rsys[s]) * ((o->nrhs[s] + Rsys[s] - 1) / Rsys[s]);
+    single[s] = per_iter[s] * iters * 1.25;
+    work[s] = per_iter[s] * iters * team_tiles(s);
+  }
+  std::vector<int32_t> by(ns);
+  for (int32_t s = 0; s < ns; ++s) by[s] = s;
+  std::stable_sort(by.begin(), by.end(), [&](int32_t p, int32_t q) { return single[p] > single[q]; });
+  // heaviest first: a system becomes a team while its single tile outlasts the average load of a
+  // compute unit over the other ordinary tiles
+  double rest = *total;
+  std::vector<int32_t> chosen;
+  std::vector<int> pmin(ns, 0);
+  for (int32_t s : by) {
+    if (b->last_iters[s] <= 0) continue;
+    if (single[s] <= (rest - load[s]) / cus) break;
+    if (2.0 * per_iter[s] * esz / kCuBytesPerSec < 2.0 * kTeamIterSec) continue;
+    pmin[s] = min_P(s);
+    if (pmin[s] == 0) continue;
+    chosen.push_back(s);
+    rest -= load[s];
+    if ((int)chosen.size() >= cus / 8) break;
+  }
+  // workgroups in proportion to the work, at least the LDS minimum each, all compute units in
+  // total; the lightest teams go back to ordinary tiles while the minimum sizes do not fit
+  while (!chosen.empty()) {
+    int need = 0;
+    double W = 0.0;
+    for (int32_t s : chosen) {
+      need += pmin[s] * team_tiles(s);
+      W += work[s];
+    }
+    if (need > cus) {
+      rest += load[chosen.back()];
+      chosen.pop_back();
+      continue;
+    }
+    int used = 0;
+    for (int32_t s : chosen) {
+      int P = (int)((double)cus * work[s] / W / team_tiles(s));
+      P = P < pmin[s] ? pmin[s] : (P > kTeamMaxWgs ? kTeamMaxWgs : P);
+      b->team_P[s] = P;
+      used += P * team_tiles(s);
+    }
+    while (used > cus) {  // trim the largest teams
+      int32_t big = -1;
+      for (int32_t s : chosen)
+        if (b->team_P[s] > pmin[s] && (big < 0 || b->team_P[s] > b->team_P[big])) big = s;
+      if (big < 0) break;
+      --b->team_P[big];
+      used -= team_tiles(big);
+    }
+    break;
+  }
+  *total = rest;
+  return REBK_OK;
+}
+
 // Run the batch once with configuration c.  Fills out (may be NULL) and *ms.
 int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, rebk_batch_rhs_t* out, double* ms,
               int* overall) {
@@ -677,6 +787,7 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
     int32_t sys, rhs0, R;
     int64_t rhs_index;  // global index of the tile's first right-hand side
     double cost;
+    int32_t P;          // workgroups of its team (0: one workgroup)
   };
   std::vector<Tile> tiles;
   std::vector<int64_t> rhs_base(ns + 1, 0);
@@ -702,8 +813,11 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
     const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
     total += per_iter * iters * (1.0 + 0.25 * Rsys[s]) * ((o->nrhs[s] + Rsys[s] - 1) / Rsys[s]);
   }
+  int rc = plan_teams(b, o, Rsys, &total);
+  if (rc != REBK_OK) return rc;
   const double per_cu_load = total / (b->cus > 0 ? b->cus : 1);
   for (int32_t s = 0; s < ns; ++s) {
+    if (b->team_P[s] > 0) continue;
     if (b->last_iters[s] <= 0) continue;  // no previous solve: nothing to go by
     const rebk_handle* h = b->hs[s];
     const double per_iter = (double)h->m * h->max_nJ + (double)h->max_nI * h->n;
@@ -717,9 +831,15 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
     const double iters = b->last_iters[s] > 0 ? (double)b->last_iters[s] : 1.0;
     int32_t done = 0;
     while (done < o->nrhs[s]) {
+      if (b->team_P[s] > 0) {  // team tiles of up to kTeamR right-hand sides
+        const int R = o->nrhs[s] - done < rebk::kTeamR ? o->nrhs[s] - done : rebk::kTeamR;
+        tiles.push_back({s, done, R, rhs_base[s] + done, per_iter * iters, b->team_P[s]});
+        done += R;
+        continue;
+      }
       int R = Rfit;
       while (R > o->nrhs[s] - done) R >>= 1;
-      tiles.push_back({s, done, R, rhs_base[s] + done, per_iter * iters * (1.0 + 0.25 * R)});
+      tiles.push_back({s, done, R, rhs_base[s] + done, per_iter * iters * (1.0 + 0.25 * R), 0});
       done += R;
     }
   }
@@ -774,7 +894,7 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   for (int wi = 0; wi < 3; ++wi) {
     std::vector<int32_t> idx;
     for (size_t q = 0; q < tiles.size(); ++q)
-      if (tiles[q].R == kWidths[wi]) {
+      if (tiles[q].P == 0 && tiles[q].R == kWidths[wi]) {
         idx.push_back((int32_t)q);
         const rebk_handle* h = b->hs[tiles[q].sys];
         const size_t lds = rebk::batch_lds_bytes(h->m, h->n, kWidths[wi], b->max_nJ, b->max_nI, c.threads);
@@ -785,10 +905,15 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
     seg_len[wi] = ord.size();
     order.insert(order.end(), ord.begin(), ord.end());
   }
+  // the team tiles, after the others
+  const size_t team_off = order.size();
+  for (size_t q = 0; q < tiles.size(); ++q)
+    if (tiles[q].P > 0) order.push_back((int32_t)q);
+  const size_t nteam = order.size() - team_off;
   const size_t ntask = order.size();
   if (ntask > (size_t)INT32_MAX) return fail(REBK_ERR_INVALID, "too many tasks");
   const size_t nrhs_total = (size_t)rhs_base[ns];
-  int rc = grow(b->tasks_d, b->tasks_cap, ntask);
+  rc = grow(b->tasks_d, b->tasks_cap, ntask);
   if (rc == REBK_OK) rc = grow(b->iters_d, b->iters_cap, ntask);
   if (rc == REBK_OK) rc = grow(b->status_d, b->status_cap, ntask);
   if (rc == REBK_OK) rc = grow(b->err2_d, b->err2_cap, nrhs_total);
@@ -831,9 +956,59 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
       return fail(REBK_ERR_INVALID, "batch kernel cannot run with %zu bytes of LDS and %d threads", seg_lds[wi],
                   c.threads);
   }
+  // teams: workgroups [wg0, wg0 + P) of one cooperative launch per team tile; each team's
+  // reduction words (2 P partial vectors and 2 reduced vectors of E tagged pairs) in one zeroed
+  // buffer that ends with the timeout flag
+  const int32_t E = rebk::kTeamR * (b->max_nJ + b->max_nI + 1);
+  std::vector<rebk::TeamTask> teams(nteam);
+  std::vector<int32_t> team_of_wg;
+  size_t team_lds = 0, tsync_words = 0;
+  for (size_t q = 0; q < nteam; ++q) {
+    const Tile& tl = tiles[order[team_off + q]];
+    const rebk_handle* h = b->hs[tl.sys];
+    const size_t lds = rebk::team_lds_bytes(h->m, h->n, tl.P, b->max_nJ, b->max_nI, b->panel_dtype);
+    if (lds > team_lds) team_lds = lds;
+    teams[q].task = (int32_t)(team_off + q);
+    teams[q].P = tl.P;
+    teams[q].wg0 = (int32_t)team_of_wg.size();
+    teams[q].E = E;
+    team_of_wg.insert(team_of_wg.end(), (size_t)tl.P, (int32_t)q);
+    tsync_words += (2 * (size_t)tl.P + 2) * E * 2;
+  }
+  if (nteam > 0) {
+    int per_cu = 0;
+    HIP_TRY(rebk::team_max_blocks(b->panel_dtype, team_lds, &per_cu));
+    if (per_cu <= 0 || team_of_wg.size() > (size_t)per_cu * (size_t)(b->cus > 0 ? b->cus : 1))
+      return fail(REBK_ERR_INVALID, "teams need %zu workgroups at once; the device holds %d with %zu bytes of LDS",
+                  team_of_wg.size(), per_cu * b->cus, team_lds);
+    rc = grow(b->teams_d, b->teams_cap, nteam);
+    if (rc == REBK_OK) rc = grow(b->team_of_wg_d, b->twg_cap, team_of_wg.size());
+    if (rc == REBK_OK) rc = grow(b->tsync_d, b->tsync_cap, tsync_words + 1);
+    if (rc != REBK_OK) return rc;
+    size_t off = 0;
+    for (size_t q = 0; q < nteam; ++q) {
+      teams[q].part = b->tsync_d + off;
+      off += 2 * (size_t)teams[q].P * E * 2;
+      teams[q].sum = b->tsync_d + off;
+      off += 2 * (size_t)E * 2;
+    }
+  }
   hipStream_t st = b->stream;
   HIP_TRY(hipMemcpyAsync(b->tasks_d, tasks.data(), ntask * sizeof(rebk::BatchTask), hipMemcpyHostToDevice, st));
+  if (nteam > 0) {
+    HIP_TRY(hipMemcpyAsync(b->teams_d, teams.data(), nteam * sizeof(rebk::TeamTask), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->team_of_wg_d, team_of_wg.data(), team_of_wg.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(b->tsync_d, 0, (tsync_words + 1) * sizeof(unsigned long long), st));
+  }
   HIP_TRY(hipEventRecord(b->ev0, st));
+  if (nteam > 0) {  // the teams first, on the batch's stream; the other tiles start after them
+    rebk::TeamArgs ta{};
+    ta.teams = b->teams_d;
+    ta.team_of_wg = b->team_of_wg_d;
+    ta.timeout = (int*)(b->tsync_d + tsync_words);
+    HIP_TRY(rebk::launch_team_solve(a, ta, (int)team_of_wg.size(), b->panel_dtype, team_lds, st));
+  }
   // the first non-empty width runs on the caller's stream, the others on the side streams, all at
   // the same time; the caller's stream then waits for them
   int nside = 0;
@@ -865,7 +1040,11 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
   HIP_TRY(hipMemcpyAsync(stt.data(), b->status_d, ntask * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(e2.data(), b->err2_d, nrhs_total * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(x2.data(), b->xref2_d, nrhs_total * sizeof(double), hipMemcpyDeviceToHost, st));
+  int timed_out = 0;
+  if (nteam > 0)
+    HIP_TRY(hipMemcpyAsync(&timed_out, b->tsync_d + tsync_words, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (timed_out) return fail(REBK_ERR_TIMEOUT, "a team reduction exceeded its spin limit");
   float fms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&fms, b->ev0, b->ev1));
   if (ms) *ms = fms;
@@ -884,6 +1063,7 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
         r.iterations = it[w];
         r.status = s_;
         r.tile = tl.R;
+        r.team = tl.P;
         const double ee = e2[tl.rhs_index + k], xx = x2[tl.rhs_index + k];
         r.rel_err = (o->x_ref_dev && ee >= 0.0 && xx > 0.0) ? std::sqrt(ee) / std::sqrt(xx) : -1.0;
       }
@@ -933,6 +1113,7 @@ int rebk_batch_create(rebk_batch_t* out, int32_t nsys, const rebk_handle_t* syst
   b->cus = systems[0]->cus;
   b->hs.assign(systems, systems + nsys);
   b->last_iters.assign(nsys, 0);
+  b->team_P.assign(nsys, 0);
   std::vector<rebk::BatchSys> S(nsys);
   for (int32_t s = 0; s < nsys; ++s) {
     const rebk_handle* h = systems[s];

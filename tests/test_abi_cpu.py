@@ -66,3 +66,37 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_native, "_lib", None)
     with pytest.raises(_native.NativeLibraryMissing):
         _native.load()
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Sizes and field offsets of the option and result structs, as the C compiler lays them out
+    from the header, equal those of the binding's ctypes mirrors."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_2001_04179_amd import _native as N
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"rebk_solve_opts_t": N.SolveOpts, "rebk_result_t": N.Result, "rebk_refine_opts_t": N.RefineOpts,
+               "rebk_batch_opts_t": N.BatchOpts, "rebk_batch_rhs_t": N.BatchRhs}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", "#include \"rebk.h\"", "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
