@@ -1010,14 +1010,15 @@ int batch_run(rebk_batch* b, const rebk_batch_opts_t* o, const BatchConfig& c, r
     HIP_TRY(rebk::launch_team_solve(a, ta, (int)team_of_wg.size(), b->panel_dtype, team_lds, st));
   }
   // the first non-empty width runs on the caller's stream, the others on the side streams, all at
-  // the same time; the caller's stream then waits for them
+  // the same time; the caller's stream then waits for them.  The fork is recorded before the
+  // first width is queued (after the teams), so the side streams do not wait for that kernel.
   int nside = 0;
   bool first = true;
+  HIP_TRY(hipEventRecord(b->fork, st));
   for (int wi = 0; wi < 3; ++wi) {
     if (seg_len[wi] == 0) continue;
     hipStream_t ls = st;
     if (!first) {
-      if (nside == 0) HIP_TRY(hipEventRecord(b->fork, st));
       ls = b->side[nside];
       HIP_TRY(hipStreamWaitEvent(ls, b->fork, 0));
     }

@@ -514,7 +514,8 @@ __global__ void __launch_bounds__(T) team_solve_kernel(BatchArgs a, TeamArgs ta)
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
         const int ia = i0 + li < nitems ? i0 + li : nitems - 1;
         const bool a_on = i0 + li < nitems;
-        for (int t0 = 0; t0 < len; t0 += 4) {
+#pragma unroll 4
+        for (int t0 = 0; t0 < len; t0 += 4) {  // (unrolled: the LDS operand loads overlap)
           const int t = t0 + lt;
           const bool on = t < len;
           const int tc = on ? t : len - 1;
