@@ -238,10 +238,24 @@ __global__ void __launch_bounds__(T) team_solve_kernel(BatchArgs a, TeamArgs ta)
   // entry of the row slab, or the start of the row panel), so they are all in flight at once.
   auto fetch = [&](const SlabCopy& sc, TP (&pre)[kPre]) {
     if (sc.total == 0) return;
+    // column-slab entry e = c nr + q: (c, q) of e = tid + j T follow from those of j - 1 by adding
+    // (T / nr, T mod nr) with a carry
+    const int nrr = nr > 0 ? nr : 1;
+    int qT;
+    const int cT = div_by(T, nrr, sc.inv_nr, qT);
+    int q0;
+    int c0 = div_by(tid, nrr, sc.inv_nr, q0);
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
       const int e = tid + j * T;
-      pre[j] = *src_of(sc, e < sc.total ? e : sc.CT);
+      const GAS TP* src = e < sc.CT ? sc.c + (int64_t)c0 * S.ldc + q0 : sc.r + ((e < sc.total ? e : sc.CT) - sc.CT);
+      pre[j] = *src;
+      q0 += qT;
+      c0 += cT;
+      if (q0 >= nrr) {
+        q0 -= nrr;
+        ++c0;
+      }
     }
   };
   auto place = [&](const SlabCopy& sc, TP (&pre)[kPre]) {
@@ -514,14 +528,18 @@ __global__ void __launch_bounds__(T) team_solve_kernel(BatchArgs a, TeamArgs ta)
         f64x4 acc = {0.0, 0.0, 0.0, 0.0};
         const int ia = i0 + li < nitems ? i0 + li : nitems - 1;
         const bool a_on = i0 + li < nitems;
-#pragma unroll 4
-        for (int t0 = 0; t0 < len; t0 += 4) {  // (unrolled: the LDS operand loads overlap)
-          const int t = t0 + lt;
-          const bool on = t < len;
-          const int tc = on ? t : len - 1;
-          const double av = (a_on && on) ? widen(M[ia * si + tc * st]) : 0.0;
-          const double bv = on ? w[li * ws + tc] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        for (int t0 = 0; t0 < len; t0 += 16) {  // operands of 4 steps loaded first, so they overlap
+          double av[4], bv[4];
+#pragma unroll
+          for (int u4 = 0; u4 < 4; ++u4) {
+            const int t = t0 + 4 * u4 + lt;
+            const bool on = t < len;
+            const int tc = on ? t : len - 1;
+            av[u4] = (a_on && on) ? widen(M[ia * si + tc * st]) : 0.0;
+            bv[u4] = on ? w[li * ws + tc] : 0.0;
+          }
+#pragma unroll
+          for (int u4 = 0; u4 < 4; ++u4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u4], bv[u4], acc, 0, 0, 0);
         }
         const int k = li;
 #pragma unroll
