@@ -535,8 +535,12 @@ __global__ void __launch_bounds__(T) team_solve_kernel(BatchArgs a, TeamArgs ta)
             const int t = t0 + 4 * u4 + lt;
             const bool on = t < len;
             const int tc = on ? t : len - 1;
-            av[u4] = (a_on && on) ? widen(M[ia * si + tc * st]) : 0.0;
-            bv[u4] = on ? w[li * ws + tc] : 0.0;
+            // unconditional loads from clamped (valid) addresses, masked afterwards: a load under
+            // a branch would wait for itself before the next one
+            const double a = widen(M[ia * si + tc * st]);
+            const double b = w[li * ws + tc];
+            av[u4] = (a_on && on) ? a : 0.0;
+            bv[u4] = on ? b : 0.0;
           }
 #pragma unroll
           for (int u4 = 0; u4 < 4; ++u4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u4], bv[u4], acc, 0, 0, 0);
