@@ -210,9 +210,9 @@ __global__ void __launch_bounds__(T) team_solve_kernel(BatchArgs a, TeamArgs ta)
   // This round's two slabs: the column slab of iteration qc (owned rows of the nJ columns of J;
   // column panels hold A^T, so each column is a run of the owned rows; entry (q, c) goes to
   // c * SC + q) and the row slab of iteration qr (owned columns of I: one run of nc x nI entries
-  // of the column-major row panel; entry (l, c) goes to c * SR + l).  fetch() issues the first
-  // kPre entries of each thread into registers; the updates run while they land; place() stores
-  // them and copies the rest.
+  // of the column-major row panel; entry (l, c) goes to c * SR + l).  fetch(), called before the
+  // previous round's reduction, issues the first kPre entries of each thread into registers;
+  // place(), after this round's updates, stores them and copies the rest.
   struct SlabCopy {
     const GAS TP* c;  // column slab source (NULL: none)
     const GAS TP* r;  // row slab source
@@ -281,8 +281,8 @@ __global__ void __launch_bounds__(T) team_solve_kernel(BatchArgs a, TeamArgs ta)
     }
   };
 
-  // Partial vectors.  Entries of a round: [0, nk nJ) v (k nJ + c), then nk nI of u (k nI + l),
-  // then nk errors (k).
+  // Partial vectors: the entries of a round are [0, nk nJ) of v (k nJ + c), then nk nI of u
+  // (k nI + l), then nk errors (k).
   // ||x - x_ref||^2 (or ||x_ref||^2 with ref_only) over owned columns, wave w taking the
   // right-hand sides w, w + 4, ...
   auto part_err = [&](GAS u64* Pw, int base, unsigned ep, bool ref_only) {
