@@ -10,6 +10,13 @@ plus rebk_solve_ex to the tolerance, inputs resident in HBM.  Both panel precisi
 (FP64 panels, the plain method; FP32 panels with FP64 iterates); the faster one that reaches the
 tolerance is the reported form.
 
+The same line carries, unless ``--no-extras`` is given, the other configurations measured in the
+same run: the 1000 x 100 FP64 system (``cfg1``: microseconds per iteration and solves per
+second), the 256-system batch with 16 right-hand sides each (``batched``, against plain FP64 REBK
+on every system) and the 2000 x 50000 mixed-precision refinement at 1e-6 and 1e-10 (``mixed``).
+The CPU baselines are the plain FP64 oracle on one thread (``cpu_baseline``) and its OpenMP
+variant on the host's cores (``cpu_baseline_openmp``), each on a bounded sample.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused: the program runs on one GPU.
 """
 from __future__ import annotations
@@ -51,6 +58,10 @@ def parse():
     p.add_argument("--grid-wgs", type=int, default=0)
     p.add_argument("--panels", default="f64,f32")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extras", action="store_true",
+                   help="only the 20000 x 2000 headline (no cfg1 / batched / mixed sub-results)")
+    p.add_argument("--omp-sample-iters", type=int, default=24000,
+                   help="oracle iterations timed for the OpenMP CPU baseline")
     p.add_argument("--cpu-sample-iters", type=int, default=12000,
                    help="oracle iterations timed for the CPU baseline (about 11 s on one core)")
     p.add_argument("--scale", type=int, default=1, help="divide the problem dimensions (quick checks only)")
@@ -164,12 +175,86 @@ def cpu_baseline(S, iters_to_tol, sample_iters):
     }
 
 
+def host_description():
+    """Cores and CPU model of the host the CPU baselines ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"nproc": affinity, "os_cpu_count": os.cpu_count(), "cpu_model": model,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline_openmp(S, iters_to_tol, sample_iters):
+    """The oracle's iteration with its block products on OpenMP threads (all the host cores
+    OpenMP is given), timed on a bounded sample and scaled to the solve's iteration count."""
+    import oracle
+    threads = oracle.omp_threads()
+    oracle.rebk_solve_omp(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=50)  # warm caches / threads
+    t0 = time.perf_counter()
+    oracle.rebk_solve_omp(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=sample_iters)
+    per_iter = (time.perf_counter() - t0) / sample_iters
+    return {
+        "value": 1.0 / (per_iter * iters_to_tol),
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle-openmp",
+        "sample": f"{sample_iters} iterations of the same workload (the oracle's iteration with its block products "
+                  f"on {threads} OpenMP threads), {per_iter * 1e3:.4f} ms/iteration, scaled to the {iters_to_tol} "
+                  f"iterations the solve needs",
+        "host": host_description(),
+    }
+
+
+def sub_cfg1(rebk, steps, warmup, tol):
+    """The 1000 x 100 dense Gaussian FP64 system (10 row blocks of 100, 10 column blocks of 10,
+    alpha = 1 / beta_max, seed 0) to relative error 1e-6: time per solve and per iteration with
+    the automatic kernel choice and with each kernel."""
+    import torch
+    from paper_2001_04179_amd import workloads as W
+    S = W.dense_gaussian_1000x100()
+    dev = torch.device("cuda:0")
+    A_d, b_d, xr_d = (torch.from_numpy(v).to(dev) for v in (S.A, S.b, S.x_ref))
+    sv = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, S.seed, panel_dtype="f64")
+    out = {"workload": "dense N(0,1) 1000 x 100, 100-row / 10-column blocks, FP64, tol %g" % tol}
+    for kernel in ("auto", "workgroup", "grid"):
+        for _ in range(warmup):
+            sv.solve_ex(b_d, max_iter=200000, x_ref=xr_d, tol=tol, check_every=1, kernel=kernel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o = sv.solve_ex(b_d, max_iter=200000, x_ref=xr_d, tol=tol, check_every=1, kernel=kernel)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        r = o["result"]
+        x = o["x"].cpu().numpy()
+        out[kernel] = {"kernel": r.kernel, "status": r.status, "iterations": r.iterations,
+                       "rel_err": float(np.linalg.norm(x - S.x_ref) / np.linalg.norm(S.x_ref)),
+                       "ms_per_solve": wall * 1e3, "solves_per_s": 1.0 / wall,
+                       "device_ms": r.time_ms, "us_per_iter": r.time_ms * 1e3 / max(1, r.iterations),
+                       "kernel_GBs": 8 * (1000 * 10 + 100 * 100) * r.iterations / (r.time_ms * 1e-3) / 1e9}
+    sv.close()
+    return out
+
+
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
 
 
-def bench_batched(args):
-    """256 independent dense systems x 16 right-hand sides, one batched launch per step, to
-    relative error 1e-6 for every right-hand side (checked every 16 iterations)."""
+def run_batched(args, steps, warmup, with_cpu):
+    """256 independent dense systems x 16 right-hand sides, one batched call per step, to relative
+    error tol for every right-hand side (checked every 16 iterations), after one autotuner pass.
+    Plain FP64 REBK (FP64 panels, one system at a time, the same check cadence) runs the first
+    right-hand side of every system; its total is that time times the system's right-hand sides.
+    Returns a dict (the batched bench line's fields)."""
     import torch
     import paper_2001_04179_amd as rebk
     from paper_2001_04179_amd import workloads as W
@@ -198,21 +283,20 @@ def bench_batched(args):
     def one():
         return batch.solve(B, x_ref=XR, max_iter=2_000_000, tol=args.tol, check_every=16)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs = [one() for _ in range(args.steps)]
+    outs = [one() for _ in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = outs[-1]
     nrhs_total = int(sum(S.B.shape[0] for S in systems))
     # true error against A^+ b of every right-hand side
     errs = []
-    for s, S in enumerate(systems):
-        X = out["x"][s].cpu().numpy()
-        for k in range(S.B.shape[0]):
-            errs.append(float(np.linalg.norm(X[k] - S.X_ref[k]) / np.linalg.norm(S.X_ref[k])))
+    for s_, S in enumerate(systems):
+        X = out["x"][s_].cpu().numpy()
+        errs.extend(np.linalg.norm(X - S.X_ref, axis=1) / np.linalg.norm(S.X_ref, axis=1))
     kernel_ms = float(np.mean([o["time_ms"] for o in outs]))
     # algorithmic panel bytes: each system-iteration reads its two blocks once (shared by the
     # right-hand sides solved together through L2); flops: 4 (m |J| + |I| n) per right-hand side
@@ -220,63 +304,58 @@ def bench_batched(args):
     bytes_alg = 0.0
     flops = 0.0
     q = 0
-    for s, S in enumerate(systems):
+    per_system = []
+    for S in systems:
         m, n = S.A.shape
+        k = S.B.shape[0]
         per = (m * (n / (len(S.col_off) - 1)) + (m / (len(S.row_off) - 1)) * n)  # mean elements per iteration
-        its = out["iterations"][q:q + S.B.shape[0]]
+        its = out["iterations"][q:q + k]
         bytes_alg += esz * per * float(np.max(its))
         flops += 4.0 * per * float(np.sum(its))
-        q += S.B.shape[0]
-    per_system = []
-    q = 0
-    for S in systems:
-        k = S.B.shape[0]
-        per_system.append([int(S.A.shape[0]), int(S.A.shape[1]), getattr(S, "rank", None),
-                           int(np.max(out["tile"][q:q + k])), int(np.max(out["iterations"][q:q + k]))])
+        per_system.append([int(m), int(n), getattr(S, "rank", None), int(np.max(out["tile"][q:q + k])),
+                           int(np.max(its))])
         q += k
     gbs = bytes_alg / (kernel_ms * 1e-3) / 1e9
     tflops = flops / (kernel_ms * 1e-3) / 1e12
-    # plain FP64 REBK on the same inputs, one right-hand side at a time (sampled systems)
-    plain = []
-    pick = list(range(0, len(systems), max(1, len(systems) // max(1, args.batch_plain_sample))))[:args.batch_plain_sample]
-    for sidx in pick:
-        S = systems[sidx]
+    # plain FP64 REBK on the same inputs: the first right-hand side of every system, alone, with the
+    # batch's check cadence; a system's total is that time times its right-hand sides
+    plain_s, plain_its = [], []
+    t_plain0 = time.perf_counter()
+    for sidx, S in enumerate(systems):
         A_d = torch.from_numpy(S.A).to(dev)
         sv = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, 0, panel_dtype="f64")
         del A_d
-        t1 = time.perf_counter()
-        o = sv.solve_ex(B[sidx][0].contiguous(), x_ref=XR[sidx][0].contiguous(), tol=args.tol, check_every=1,
-                        max_iter=2_000_000)
+        b0, x0r = B[sidx][0].contiguous(), XR[sidx][0].contiguous()
         torch.cuda.synchronize()
-        plain.append({"system": sidx, "shape": list(S.A.shape), "seconds": time.perf_counter() - t1,
-                      "iterations": o["result"].iterations, "kernel": o["result"].kernel, "status": o["result"].status})
+        t1 = time.perf_counter()
+        o = sv.solve_ex(b0, x_ref=x0r, tol=args.tol, check_every=16, max_iter=2_000_000)
+        torch.cuda.synchronize()
+        plain_s.append((time.perf_counter() - t1) * S.B.shape[0])
+        plain_its.append(o["result"].iterations)
         sv.close()
-    plain_total_est = float(np.mean([p["seconds"] for p in plain])) * nrhs_total
-    value = nrhs_total / (wall / args.steps)
-    line = {
-        "metric": "time & iters to rel err 1e-6 (solves/s, GB/s vs roofline), chosen form vs plain REBK",
-        "value": value,
+    t_plain = time.perf_counter() - t_plain0
+    plain_total = float(np.sum(plain_s))
+    step_s = wall / steps
+    res = {
+        "value": nrhs_total / step_s,
         "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"batched: {len(systems)} dense systems (m, n in [500, 8000] x [100, 2000], aspect >= 4, "
-                               f"odd ones transposed, every 4th rank min/2) x 16 right-hand sides, blocks 64 x 16, "
-                               f"tol {args.tol:g}", "panel_dtype": args.batch_panels, "systems": len(systems),
-                   "rhs_total": nrhs_total, "tuned": tuned},
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": step_s * 1e3,
+        "workload": f"batched: {len(systems)} dense systems (m, n in [500, 8000] x [100, 2000], aspect >= 4, "
+                    f"odd ones transposed, every 4th rank min/2) x 16 right-hand sides, blocks 64 x 16, "
+                    f"tol {args.tol:g}",
+        "panel_dtype": args.batch_panels, "systems": len(systems), "rhs_total": nrhs_total, "tuned": tuned,
         "status": out["status"],
         "iterations": {"min": int(out["iterations"].min()), "median": float(np.median(out["iterations"])),
                        "max": int(out["iterations"].max()), "sum": int(out["iterations"].sum())},
         "rel_err_max": float(max(errs)),
         "kernel_ms": kernel_ms,
-        "speedup_vs_plain_f64_est": plain_total_est / (wall / args.steps),
-        "plain_f64_sample": plain,
+        "plain_f64": {"seconds_est": plain_total, "solves_per_s_est": nrhs_total / plain_total,
+                      "how": "plain FP64 REBK, one right-hand side at a time with check_every 16: the first "
+                             "right-hand side of every system timed alone, times the system's right-hand sides",
+                      "iterations_sum_first_rhs": int(np.sum(plain_its)), "measured_seconds": t_plain},
+        "speedup_vs_plain_f64": plain_total / step_s,
         "prep_seconds": {"generate": t_gen, "create": t_create, "autotune": t_tune},
         # per system: rows, columns, rank (null: full), tile width, most iterations of a right-hand side
         "per_system": per_system,
@@ -285,34 +364,50 @@ def bench_batched(args):
                      "fp64_tflops": tflops, "fp64_peak_tflops": FP64_PEAK_TFLOPS,
                      "fp64_frac": tflops / FP64_PEAK_TFLOPS},
     }
-    if not args.no_cpu_baseline:
+    if with_cpu:
         import oracle
-        # the oracle on the first right-hand side of a few systems, 400 iterations each, scaled to
+        # the oracle on the first right-hand side of four systems, 400 iterations each, scaled to
         # the iterations the batch ran
+        pick = list(range(0, len(systems), max(1, len(systems) // 4)))[:4]
         t_sum, it_sum = 0.0, 0
-        for sidx in pick[:4]:
+        for sidx in pick:
             S = systems[sidx]
             t1 = time.perf_counter()
             oracle.rebk_solve(stored(S.A) if stored else S.A, S.row_off, S.col_off, S.alpha, 0, S.B[0], max_iter=400,
                               sys=S.sys_id, trace=False)
             t_sum += time.perf_counter() - t1
             it_sum += 400
-        # seconds per iteration of a system, averaged over the sample, times all right-hand-side iterations
         per_it = t_sum / it_sum
         total = per_it * float(out["iterations"].sum())
-        line["cpu_baseline"] = {"value": nrhs_total / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                                "sample": f"FP64 C oracle, single thread: 400 iterations of the first right-hand side "
-                                          f"of systems {pick[:4]}, {per_it * 1e3:.3f} ms/iteration, scaled to the "
-                                          f"{int(out['iterations'].sum())} right-hand-side iterations of the batch"}
+        res["cpu_baseline"] = {"value": nrhs_total / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 C oracle, single thread: 400 iterations of the first right-hand side "
+                                         f"of systems {pick}, {per_it * 1e3:.3f} ms/iteration, scaled to the "
+                                         f"{int(out['iterations'].sum())} right-hand-side iterations of the batch"}
     batch.close()
     for sv in solvers:
         sv.close()
+    return res
+
+
+def bench_batched(args):
+    r = run_batched(args, args.steps, args.warmup, not args.no_cpu_baseline)
+    line = {
+        "metric": "time & iters to rel err 1e-6 (solves/s, GB/s vs roofline), chosen form vs plain REBK",
+        "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": r["steps"], "warmup": r["warmup"],
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r["workload"], "panel_dtype": r["panel_dtype"], "systems": r["systems"],
+                   "rhs_total": r["rhs_total"], "tuned": r["tuned"]},
+    }
+    line.update({k: v for k, v in r.items() if k not in ("value", "unit", "steps", "warmup", "ms_per_step",
+                                                         "workload", "panel_dtype", "systems", "rhs_total",
+                                                         "tuned")})
     print(json.dumps(line))
 
 
-def bench_mixed(args):
+def run_mixed(args, steps, warmup, inner_list, with_cpu):
     """2000 x 50000 rank-1200 system: plain FP64 REBK (FP64 panels) against BF16 / FP16 panels with
-    FP64 refinement, time to relative error 1e-6 and 1e-10 against A^+ b."""
+    FP64 refinement, time to relative error 1e-6 and 1e-10 against A^+ b.  Returns a dict."""
     import torch
     import paper_2001_04179_amd as rebk
     from paper_2001_04179_amd import workloads as W
@@ -331,13 +426,13 @@ def bench_mixed(args):
     sv = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, S.seed, panel_dtype="f64")
     for tol in tols:
         runs = []
-        for _ in range(args.warmup + args.steps):
+        for _ in range(warmup + steps):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             o = sv.solve_ex(b_d, x_ref=xr_d, tol=tol, check_every=1, max_iter=5_000_000, kernel="grid")
             torch.cuda.synchronize()
             runs.append((time.perf_counter() - t1, o))
-        wall = float(np.mean([r[0] for r in runs[args.warmup:]]))
+        wall = float(np.mean([r[0] for r in runs[warmup:]]))
         o = runs[-1][1]
         x = o["x"].cpu().numpy()
         res["plain_f64"][f"{tol:g}"] = {"seconds": wall, "iterations": o["result"].iterations,
@@ -346,21 +441,19 @@ def bench_mixed(args):
                                         "us_per_iter": o["result"].time_ms * 1e3 / max(1, o["result"].iterations)}
         print(f"# plain f64 tol {tol:g}: {json.dumps(res['plain_f64'][f'{tol:g}'])}", file=sys.stderr, flush=True)
     sv.close()
-    inner_list = [int(v) for v in args.mixed_inner.split(",")]
-    best = None
     for panel in ("bf16", "f16"):
         sv = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
         for inner in inner_list:
             for tol in tols:
                 runs = []
-                for _ in range(args.warmup + args.steps):
+                for _ in range(warmup + steps):
                     torch.cuda.synchronize()
                     t1 = time.perf_counter()
                     o = sv.solve_refined(A_d, b_d, x_ref=xr_d, tol=tol, inner_iters=inner, max_outer=200,
                                          kernel="grid")
                     torch.cuda.synchronize()
                     runs.append((time.perf_counter() - t1, o))
-                wall = float(np.mean([r[0] for r in runs[args.warmup:]]))
+                wall = float(np.mean([r[0] for r in runs[warmup:]]))
                 o = runs[-1][1]
                 x = o["x"].cpu().numpy()
                 entry = {"panel": panel, "inner_iters": inner, "tol": tol, "seconds": wall,
@@ -369,8 +462,6 @@ def bench_mixed(args):
                          "rel_err": float(np.linalg.norm(x - S.x_ref) / np.linalg.norm(S.x_ref))}
                 res["refined"].setdefault(panel, []).append(entry)
                 print(f"# refined {json.dumps(entry)}", file=sys.stderr, flush=True)
-                if tol == tols[-1] and entry["status"] == "ok" and (best is None or wall < best["seconds"]):
-                    best = entry
         sv.close()
     # per tolerance: the fastest refined form against plain FP64
     summary = {}
@@ -379,21 +470,18 @@ def bench_mixed(args):
         fastest = min(cands, key=lambda e: e["seconds"]) if cands else None
         plain = res["plain_f64"][f"{tol:g}"]
         summary[f"{tol:g}"] = {"plain_f64_seconds": plain["seconds"], "plain_f64_iterations": plain["iterations"],
-                               "refined": fastest,
+                               "plain_f64_rel_err": plain["rel_err"], "refined": fastest,
                                "speedup": (plain["seconds"] / fastest["seconds"]) if fastest else None}
     chosen = summary[f"{tols[-1]:g}"]["refined"] or {"seconds": float("nan"), "panel": None}
-    inner_bytes = {"bf16": 2, "f16": 2}[chosen["panel"]] * (m * 100 + 100 * n) if chosen["panel"] else None
-    line = {
-        "metric": "time & iters to rel err 1e-6 (solves/s, GB/s vs roofline), chosen form vs plain REBK",
+    inner_bytes = 2 * (m * 100 + 100 * n) if chosen["panel"] else None
+    out = {
         "value": 1.0 / chosen["seconds"],
         "unit": "solves/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "steps": steps, "warmup": warmup,
         "ms_per_step": chosen["seconds"] * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"mixed precision: A = U V ({m} x {n}, rank {1200 // args.scale}), 100-row / "
-                               f"100-column blocks, FP64 refinement to rel err 1e-10 (1e-6 also reported)",
-                   "panel_dtype": chosen["panel"], "inner_iters": chosen.get("inner_iters")},
+        "workload": f"mixed precision: A = U V ({m} x {n}, rank {1200 // args.scale}), 100-row / "
+                    f"100-column blocks, FP64 refinement to rel err 1e-10 (1e-6 also reported)",
+        "panel_dtype": chosen["panel"], "inner_iters": chosen.get("inner_iters"),
         "per_tolerance": summary,
         "runs": res,
         "roofline": {"bound": "hbm", "kernel": "grid_solve_kernel (inner)",
@@ -405,18 +493,33 @@ def bench_mixed(args):
                      "traffic": None},
         "prep_seconds": {"generate": t_gen},
     }
-    if not args.no_cpu_baseline:
+    if with_cpu:
         import oracle
         K = 20
         t1 = time.perf_counter()
         oracle.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=K, trace=False)
         per_it = (time.perf_counter() - t1) / K
         plain = summary[f"{tols[-1]:g}"]
-        line["cpu_baseline"] = {"value": 1.0 / (per_it * plain["plain_f64_iterations"]), "unit": "solves/s",
-                                "cores": 1, "kind": "oracle",
-                                "sample": f"{K} iterations of the FP64 C oracle (single thread), {per_it * 1e3:.2f} "
-                                          f"ms/iteration, scaled to the {plain['plain_f64_iterations']} iterations plain "
-                                          f"FP64 REBK needs for 1e-10"}
+        out["cpu_baseline"] = {"value": 1.0 / (per_it * plain["plain_f64_iterations"]), "unit": "solves/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{K} iterations of the FP64 C oracle (single thread), {per_it * 1e3:.2f} "
+                                         f"ms/iteration, scaled to the {plain['plain_f64_iterations']} iterations plain "
+                                         f"FP64 REBK needs for 1e-10"}
+    return out
+
+
+def bench_mixed(args):
+    r = run_mixed(args, args.steps, args.warmup, [int(v) for v in args.mixed_inner.split(",")],
+                  not args.no_cpu_baseline)
+    line = {
+        "metric": "time & iters to rel err 1e-6 (solves/s, GB/s vs roofline), chosen form vs plain REBK",
+        "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": r["steps"], "warmup": r["warmup"],
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r["workload"], "panel_dtype": r["panel_dtype"], "inner_iters": r["inner_iters"]},
+    }
+    line.update({k: v for k, v in r.items() if k not in ("value", "unit", "steps", "warmup", "ms_per_step",
+                                                         "workload", "panel_dtype", "inner_iters")})
     print(json.dumps(line))
 
 
@@ -678,6 +781,18 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(S, chosen["iterations"], args.cpu_sample_iters)
+        line["cpu_baseline_openmp"] = cpu_baseline_openmp(S, chosen["iterations"], args.omp_sample_iters)
+    del A_d, b_d, xr_d, S
+    if not args.no_extras:
+        # the other configurations, in the same run (each prints its progress on stderr)
+        line["cfg1"] = sub_cfg1(rebk, steps=max(5, args.steps), warmup=max(1, args.warmup), tol=args.tol)
+        print(f"# cfg1: {json.dumps(line['cfg1'])}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        line["batched"] = run_batched(args, steps=1, warmup=1, with_cpu=False)
+        print(f"# batched: {line['batched']['value']:.1f} solves/s", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        line["mixed"] = run_mixed(args, steps=1, warmup=1, inner_list=[2000, 4000], with_cpu=False)
+        print(f"# mixed: {json.dumps(line['mixed']['per_tolerance'])}", file=sys.stderr, flush=True)
     print(json.dumps(line))
 
 

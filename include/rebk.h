@@ -162,11 +162,24 @@ int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t *opts, rebk_result_t 
 
 /*
  * Copy the FP64 block weights to host arrays w_row (s entries, ||A_{I_i,:}||_F^2)
- * and w_col (t entries, ||A_{:,J_j}||_F^2); either may be NULL.
+ * and w_col (t entries, ||A_{:,J_j}||_F^2); either may be NULL.  Algorithm 1
+ * (Section 2) draws column block j with probability ||A_{:,J_j}||_F^2 / ||A||_F^2
+ * and row block i with probability ||A_{I_i,:}||_F^2 / ||A||_F^2; these are the
+ * numerators, summed in FP64 in a fixed order (per row, squares in ascending
+ * column order; then rows ascending; no fused multiply-add).  Errors:
+ * REBK_ERR_INVALID for a NULL handle.
  */
 int rebk_get_weights(rebk_handle_t h, double *w_row, double *w_col);
 
-/* Copy the cumulative 53-bit sampling thresholds (s and t entries) to host arrays. */
+/*
+ * Copy the sampling thresholds of Algorithm 1's two draws (Section 2) to host
+ * arrays T_row (s entries) and T_col (t entries), either may be NULL:
+ * T_j = floor(C_j / C_t * 2^53) for the prefix sums C_j of the weights above
+ * (T_t = 2^53).  A 53-bit uniform draw d picks the first block with d < T_j, so
+ * block j is drawn with probability (T_j - T_{j-1}) / 2^53, its weight's share
+ * of the total rounded to 53 bits; a zero-weight block is never drawn.
+ * Errors: REBK_ERR_INVALID for a NULL handle.
+ */
 int rebk_get_thresholds(rebk_handle_t h, uint64_t *T_row, uint64_t *T_col);
 
 /* Sizes of the handle: m, n, s, t, the largest row block and the largest column block. */
@@ -174,10 +187,15 @@ int rebk_get_info(rebk_handle_t h, int64_t *m, int64_t *n, int64_t *s, int64_t *
                   int64_t *max_row_block, int64_t *max_col_block);
 
 /*
- * Run only the block sampler of the handle on the device for iterations
- * k0+1 .. k0+count of system `system`: j_out_dev[q] and i_out_dev[q]
- * (int32, count entries each) receive the 0-based blocks of iteration
- * k0+q+1.  Synchronizes the stream.
+ * Run only the block sampler of the handle on the device: the two block
+ * draws of Algorithm 1 (Section 2; column block j first, then row block i)
+ * for iterations k0+1 .. k0+count of system `system`.  Iteration k takes the
+ * words of Philox4x64-10(counter (k-1, system, 0, 0), key (seed, 0)): the top
+ * 53 bits of word 0 draw j, those of word 1 draw i, against the thresholds of
+ * rebk_get_thresholds.  j_out_dev[q] and i_out_dev[q] (device int32, count
+ * entries each, owned by the caller) receive the 0-based blocks of iteration
+ * k0+q+1.  Synchronizes the stream.  Errors: REBK_ERR_INVALID for a NULL
+ * handle or output, count < 0 or k0 < 0; REBK_ERR_HIP.
  */
 int rebk_sample_blocks(rebk_handle_t h, uint64_t system, int64_t k0, int64_t count,
                        int32_t *j_out_dev, int32_t *i_out_dev);

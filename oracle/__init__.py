@@ -24,17 +24,32 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rebk_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
+_SRC_OMP = os.path.join(_HERE, "rebk_oracle_omp.c")
+_SRC_F32 = os.path.join(_HERE, "rebk_oracle_f32state.c")
+_LIB_OMP = os.path.join(_HERE, "liboracle_variants.so")
+
 _lib = None
+_lib_omp = None
+
+
+def _stale(lib, srcs):
+    return not os.path.exists(lib) or any(os.path.getmtime(lib) < os.path.getmtime(s) for s in srcs)
 
 
 def build(force: bool = True) -> str:
-    """Compile ``rebk_oracle.c`` into ``liboracle.so`` with gcc (no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile ``rebk_oracle.c`` into ``liboracle.so`` with gcc (no FMA contraction), and two
+    variants of the iteration that reuse its Philox and draws -- the OpenMP timing variant
+    (``rebk_oracle_omp.c``) and the all-FP32 form (``rebk_oracle_f32state.c``) -- into
+    ``liboracle_variants.so``."""
+    flags = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+    if force or _stale(_LIB, [_SRC]):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-o", tmp, _SRC, "-lm"]
-        subprocess.check_call(cmd)
+        subprocess.check_call(flags + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    if force or _stale(_LIB_OMP, [_SRC, _SRC_OMP, _SRC_F32]):
+        tmp = _LIB_OMP + ".tmp"
+        subprocess.check_call(flags + ["-fopenmp", "-o", tmp, _SRC_OMP, _SRC_F32, _SRC, "-lm"])
+        os.replace(tmp, _LIB_OMP)
     return _LIB
 
 
@@ -181,6 +196,69 @@ def rebk_solve(A, row_off, col_off, alpha, seed, b, *, x0=None, z0=None, k0=0, m
         out["j"] = jt[:k].copy()
         out["i"] = it[:k].copy()
     return out
+
+
+def _load_omp():
+    global _lib_omp
+    if _lib_omp is not None:
+        return _lib_omp
+    if _stale(_LIB_OMP, [_SRC, _SRC_OMP, _SRC_F32]):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_OMP)
+    P, I64, U64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    lib.oracle_rebk_solve_omp.argtypes = [P, I64, I64, I64, P, I64, P, I64, ctypes.c_double, U64, U64, P, I64, P, P]
+    lib.oracle_rebk_solve_omp.restype = ctypes.c_int
+    lib.oracle_omp_threads.argtypes = []
+    lib.oracle_omp_threads.restype = ctypes.c_int
+    lib.oracle_rebk_f32state.argtypes = [P, I64, I64, P, I64, P, I64, ctypes.c_double, U64, P, P, I64, I64, P, P]
+    lib.oracle_rebk_f32state.restype = ctypes.c_int
+    _lib_omp = lib
+    return lib
+
+
+def omp_threads() -> int:
+    """Threads the OpenMP variant uses (OMP_NUM_THREADS, else the cores OpenMP sees)."""
+    return int(_load_omp().oracle_omp_threads())
+
+
+def rebk_solve_omp(A, row_off, col_off, alpha, seed, b, *, max_iter=1000, sys=0):
+    """Algorithm 1 from x0 = 0, z0 = b for exactly max_iter iterations with the block products on
+    OpenMP threads (timing baseline only; the plain oracle is the parity reference).  Returns
+    dict(x, z)."""
+    lib = _load_omp()
+    A = _f64(A)
+    m, n = A.shape
+    ro, co = _i64(row_off), _i64(col_off)
+    b = _f64(b)
+    x = np.zeros(n)
+    z = np.zeros(m)
+    st = lib.oracle_rebk_solve_omp(_ptr(A), m, n, n, _ptr(ro), len(ro) - 1, _ptr(co), len(co) - 1, float(alpha),
+                                   ctypes.c_uint64(int(seed)), ctypes.c_uint64(int(sys)), _ptr(b), int(max_iter),
+                                   _ptr(x), _ptr(z))
+    if st < 0:
+        raise ValueError("invalid REBK input")
+    return {"x": x, "z": z}
+
+
+def rebk_f32state(A, row_off, col_off, alpha, seed, b, x_ref, *, max_iter=1000, every=100):
+    """Algorithm 1 from x0 = 0, z0 = b with every vector and every operation in FP32 on the FP32
+    values of A (the all-FP32 form; a measurement aid, not a parity reference).  Returns dict(x
+    (FP32), err: the relative error to x_ref every `every` iterations and at the end)."""
+    lib = _load_omp()
+    A32 = np.ascontiguousarray(A, dtype=np.float32)
+    m, n = A32.shape
+    ro, co = _i64(row_off), _i64(col_off)
+    b32 = np.ascontiguousarray(b, dtype=np.float32)
+    xr = _f64(x_ref)
+    nerr = (int(max_iter) + int(every) - 1) // int(every) + 1
+    err = np.full(nerr, np.nan)
+    x = np.zeros(n, dtype=np.float32)
+    st = lib.oracle_rebk_f32state(_ptr(A32), m, n, _ptr(ro), len(ro) - 1, _ptr(co), len(co) - 1, float(alpha),
+                                  ctypes.c_uint64(int(seed)), _ptr(b32), _ptr(xr), int(max_iter), int(every),
+                                  _ptr(err), _ptr(x))
+    if st < 0:
+        raise ValueError("invalid REBK input")
+    return {"x": x, "err": err[~np.isnan(err)]}
 
 
 def rebk_refine(A, A_stored, row_off, col_off, alpha, seed, b, *, x0=None, x_ref=None, tol=0.0, inner_iters=100,

@@ -12,7 +12,10 @@ training objective are defined here in plain numpy:
   loss = 1 / (2 batch) * sum over the batch of ||x0 - x_target||^2
 (out_scale a fixed constant, 1/sqrt(m) by default, so that y is of order one)
 
-with the backward pass of that composition and the Adam update (Kingma and Ba, ICLR 2015):
+At inference (``infer``) y is left unrounded and x0 = out_scale A^T y is formed from the FP64 A,
+so that x0 lies in range(A^T) to FP64 rounding.
+
+The backward pass of that composition and the Adam update (Kingma and Ba, ICLR 2015):
   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
   p -= lr * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
 
@@ -58,6 +61,21 @@ def forward(params, B, A, round16=False, out_scale=1.0):
     yq = r(y)
     x0 = out_scale * (yq @ r(A))
     return {"B": Bq, "h1": h1, "h2": h2, "y": y, "yq": yq, "x0": x0}
+
+
+def infer(params, B, A, out_scale=1.0):
+    """Inference start point: the network in half-precision storage as in ``forward(round16=True)``,
+    but y kept unrounded and x0 = out_scale A^T y formed from the unrounded FP64 A.  A product with
+    a rounded A would leave x0 slightly outside range(A^T), a component the x-steps of REBK never
+    remove (they only add rows of A); Theorem 7 needs x0 in range(A^T)."""
+    f = forward(params, B, A, round16=True, out_scale=out_scale)
+    y = f["y"]
+    return {"y": y, "x0": x0_of_y(y, A, out_scale)}
+
+
+def x0_of_y(Y, A, out_scale=1.0):
+    """Rows x0 = out_scale A^T y for the rows y of Y, in FP64 (A: m x n, Y: batch x m)."""
+    return out_scale * (np.asarray(Y, dtype=np.float64) @ np.asarray(A, dtype=np.float64))
 
 
 def loss_and_grads(params, B, A, Xt, round16=False, out_scale=1.0):

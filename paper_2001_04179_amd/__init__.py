@@ -6,7 +6,10 @@ library; this module only marshals arguments.  PyTorch supplies device memory an
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -56,6 +59,31 @@ def _stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+# Library objects still open when the interpreter exits are closed by an exit handler, while the HIP
+# runtime is intact: batches first (they refer to solvers), then networks, then solvers.  Finalizers
+# make no library call once the interpreter is shutting down.
+_OPEN = {"batch": weakref.WeakSet(), "net": weakref.WeakSet(), "solver": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_all():
+    for kind in ("batch", "net", "solver"):
+        for obj in list(_OPEN[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+def _finalize(obj):
+    if sys.is_finalizing():
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
+
 class Solver:
     """``rebk_create`` on a CUDA tensor A (m x n, float64 or float32, row-major).
 
@@ -88,6 +116,7 @@ class Solver:
         N.check(code, "rebk_create")
         self._h = h
         self.device = A.device
+        _OPEN["solver"].add(self)
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -96,10 +125,7 @@ class Solver:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
     def __enter__(self):
         return self
@@ -255,6 +281,7 @@ class Batch:
         N.check(lib.rebk_batch_create(ctypes.byref(b), self.nsys, ctypes.cast(hs, ctypes.c_void_p), ids,
                                       _stream_ptr()), "rebk_batch_create")
         self._b = b
+        _OPEN["batch"].add(self)
 
     def close(self):
         if getattr(self, "_b", None) and self._b.value:
@@ -262,10 +289,7 @@ class Batch:
             self._b = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
     def _opts(self, B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget, max_tile,
               xcd_order, z0_from_x0=False, team=0):
@@ -377,6 +401,7 @@ class WarmStart:
                                          _stream_ptr()),
                 "rebk_mlp_create")
         self._w = w
+        _OPEN["net"].add(self)
 
     def shapes(self):
         h, i, m = self.hidden, self.in_dim, self.m
@@ -388,10 +413,7 @@ class WarmStart:
             self._w = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self)
 
     def set_params(self, params: dict):
         arrs = [np.ascontiguousarray(params[k], dtype=np.float32) if k in params else None for k in self.NAMES]

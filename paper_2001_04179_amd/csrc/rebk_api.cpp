@@ -1705,8 +1705,9 @@ int rebk_mlp_adam(rebk_mlp_t w, double lr, double beta1, double beta2, double ep
   w->t += 1;
   const float c1 = (float)(1.0 - std::pow(beta1, (double)w->t)), c2 = (float)(1.0 - std::pow(beta2, (double)w->t));
   for (int q = 0; q < 6; ++q)
-    HIP_TRY(rebk::launch_adam(w->p[q], w->g[q], w->m1[q], w->m2[q], w->cnt[q], (float)lr, (float)beta1, (float)beta2,
-                              (float)eps, c1, c2, q % 2 == 0 ? w->w16[q / 2] : nullptr, w->stream));
+    HIP_TRY(rebk::launch_adam(w->p[q], w->g[q], w->m1[q], w->m2[q], w->cnt[q], (float)lr, (float)beta1,
+                              (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps, c1, c2,
+                              q % 2 == 0 ? w->w16[q / 2] : nullptr, w->stream));
   return REBK_OK;
 }
 

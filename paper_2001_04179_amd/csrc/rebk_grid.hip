@@ -12,7 +12,7 @@
 // Reduction: a deterministic reduce-scatter and all-gather without counters or fences.  Every
 // value crossing workgroups is published as two 64-bit atomic words that both carry the
 // iteration's epoch, so a reader can tell a current value from a stale or half-written one.  The
-// partial vector is cut into chunks of 8 entries; workgroup c owns chunk c (c, c + G, ... for
+// partial vector is cut into chunks of kChunk entries; workgroup c owns chunk c (c, c + G, ... for
 // long vectors): it polls that chunk of every workgroup's partial vector, sums the G partials in
 // a fixed order and publishes the tagged sums.  Every workgroup then reads the reduced vector
 // once.  Each sum is formed by one workgroup, so all workgroups see bit-identical reduced vectors

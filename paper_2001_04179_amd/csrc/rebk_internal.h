@@ -166,8 +166,8 @@ hipError_t launch_mlp_residual(const float* X0, const double* Xt, int64_t count,
 hipError_t launch_scale_half(const float* in, int64_t count, float s, _Float16* out, hipStream_t st);
 hipError_t launch_relu_back(const float* D, const _Float16* H, int64_t count, _Float16* out, hipStream_t st);
 hipError_t launch_colsum_half(const _Float16* D, int rows, int cols, float scale, float* out, hipStream_t st);
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
-                       float eps, float c1, float c2, _Float16* p16, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float omb1,
+                       float b2, float omb2, float eps, float c1, float c2, _Float16* p16, hipStream_t st);
 hipError_t launch_init_uniform(float* p, int64_t count, float bound, uint64_t seed, uint64_t tag, hipStream_t st);
 hipError_t launch_widen(const float* in, int64_t count, double* out, hipStream_t st);
 hipError_t launch_gemm_f64(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,

@@ -1,12 +1,6 @@
 // HIP kernels for gfx950 (MI355X): panel packing, FP64 block weights, the counter-based block
-// sampler, and the two REBK iteration kernels (Du, Si, Sun, arXiv:2001.04179, Algorithm 1).
-//
-// Cross-workgroup communication in the persistent grid kernel goes exclusively through
-// device-scope atomic operations (relaxed loads, stores and FP64 adds), which are coherent
-// across the eight XCDs without cache-maintenance fences; ordering between a workgroup's data
-// atomics and its barrier arrival is enforced by waiting for their completion
-// (s_waitcnt vmcnt(0)) before arriving.  On gfx950 an agent-scope release fence writes back the
-// whole L2 of the XCD and costs several microseconds per workgroup, which is why it is avoided.
+// sampler, the single-workgroup REBK iteration kernel and the residual / error kernels (Du, Si,
+// Sun, arXiv:2001.04179, Algorithm 1).  The whole-chip iteration kernel is in rebk_grid.hip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -168,14 +168,16 @@ __global__ void colsum_half_kernel(const _Float16* __restrict__ D, int rows, int
   out[c] = scale * s;
 }
 
-// Adam (Kingma and Ba, ICLR 2015) on one parameter array; writes the half copy (if p16)
+// Adam (Kingma and Ba, ICLR 2015) on one parameter array; writes the half copy (if p16).  omb1 and
+// omb2 are 1 - beta1 and 1 - beta2 rounded from FP64 (1 - (float)beta2 would be off by about 1e-5
+// relative for beta2 = 0.999, and the bias corrections c1, c2 are formed in FP64 too).
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int64_t count, float lr, float b1, float b2, float eps, float c1,
-                            float c2, _Float16* __restrict__ p16) {
+                            float* __restrict__ v, int64_t count, float lr, float b1, float omb1, float b2, float omb2,
+                            float eps, float c1, float c2, _Float16* __restrict__ p16) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
     const float ge = g[e];
-    const float me = b1 * m[e] + (1.f - b1) * ge;
-    const float ve = b2 * v[e] + (1.f - b2) * ge * ge;
+    const float me = b1 * m[e] + omb1 * ge;
+    const float ve = b2 * v[e] + omb2 * ge * ge;
     m[e] = me;
     v[e] = ve;
     const float pe = p[e] - lr * (me / c1) / (sqrtf(ve / c2) + eps);
@@ -269,10 +271,10 @@ hipError_t launch_colsum_half(const _Float16* D, int rows, int cols, float scale
   hipLaunchKernelGGL(colsum_half_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, D, rows, cols, scale, out);
   return hipGetLastError();
 }
-hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
-                       float eps, float c1, float c2, _Float16* p16, hipStream_t st) {
-  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(count)), dim3(256), 0, st, p, g, m, v, count, lr, b1, b2, eps, c1, c2,
-                     p16);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float omb1,
+                       float b2, float omb2, float eps, float c1, float c2, _Float16* p16, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(count)), dim3(256), 0, st, p, g, m, v, count, lr, b1, omb1, b2, omb2,
+                     eps, c1, c2, p16);
   return hipGetLastError();
 }
 hipError_t launch_init_uniform(float* p, int64_t count, float bound, uint64_t seed, uint64_t tag, hipStream_t st) {

@@ -55,8 +55,11 @@ def beta_max(A: np.ndarray, row_off, col_off):
     """(beta_max over row blocks, beta_max over column blocks): max ||B||_2^2 / ||B||_F^2."""
     def ratio(B):
         g = B @ B.T if B.shape[0] <= B.shape[1] else B.T @ B
+        tr = np.trace(g)
+        if not tr > 0.0:
+            return 0.0  # a zero block is never drawn and does not bound the stepsize
         lam = np.linalg.eigvalsh(g)[-1]
-        return float(lam / np.trace(g))
+        return float(lam / tr)
     br = max(ratio(A[row_off[i]:row_off[i + 1], :]) for i in range(len(row_off) - 1))
     bc = max(ratio(A[:, col_off[j]:col_off[j + 1]]) for j in range(len(col_off) - 1))
     return br, bc

@@ -73,6 +73,78 @@ def test_adam_step_matches_oracle(rebk):
     net.close()
 
 
+def test_adam_several_steps_match_oracle(rebk):
+    """Four Adam steps with different batches (so different gradients) and non-default decays: the
+    moments carried between steps and the bias corrections at t = 2..4 are compared, not only the
+    first step's lr sign(g)."""
+    net, A, params, B, Xt = setup(rebk, seed=6)
+    rng = np.random.default_rng(60)
+    lr, b1, b2, eps = 2e-3, 0.8, 0.95, 1e-7
+    state = {}
+    want = {k: v.copy() for k, v in params.items()}
+    for step in range(4):
+        Bs = B if step == 0 else rng.standard_normal(B.shape)
+        Xs = Xt if step == 0 else rng.standard_normal(Xt.shape)
+        net.grad(to_dev(Bs), to_dev(Xs))
+        g = {k: v.astype(np.float64) for k, v in net.grads().items()}
+        net.adam(lr, b1, b2, eps)
+        want = M.adam_step(want, g, state, lr, beta1=b1, beta2=b2, eps=eps)
+        got = net.params()
+        for k in M.PARAMS:
+            assert rel(got[k], want[k]) < 1e-6, (step, k, rel(got[k], want[k]))
+        # each step really moved the parameters by about lr (not a no-op)
+        assert np.max(np.abs(got["W1"] - params["W1"])) > 0.5 * lr
+    net.close()
+
+
+def test_inference_matches_oracle(rebk):
+    """rebk_mlp_forward against the oracle's inference: y within a few half-precision units, and
+    x0 = out_scale A^T y formed in FP64 from the FP64 A (tight against the oracle's product of the
+    GPU's y, and at the half-precision level against the oracle's own y)."""
+    net, A, params, B, Xt = setup(rebk, seed=8)
+    X0, Y = net.forward(to_dev(B), want_y=True)
+    ref = M.infer(params, B, A, out_scale=net.out_scale)
+    Yg, Xg = Y.cpu().numpy(), X0.cpu().numpy()
+    assert rel(Yg, ref["y"]) < 4 * HALF_ULP
+    assert rel(Xg, M.x0_of_y(Yg, A, net.out_scale)) < 1e-13
+    assert rel(Xg, ref["x0"]) < 4 * HALF_ULP
+    net.close()
+
+
+def test_full_size_network_matches_oracle(rebk):
+    """The warm-start workload's network at its real dimensions, 8192 -> 512 -> 512 -> 8192 with A
+    8192 x 1024 (rank 768), one batch of 64: inference, gradients and one Adam step against the
+    oracle."""
+    rng = np.random.default_rng(11)
+    m, n, in_dim, hidden, batch = 8192, 1024, 8192, 512, 64
+    A = (rng.standard_normal((m, 768)) @ rng.standard_normal((768, n))) / np.sqrt(768)
+    params = M.init_params(in_dim, hidden, m, rng)
+    for k in ("c1", "c2", "c3"):
+        params[k] = 0.05 * rng.standard_normal(params[k].shape)
+    params = {k: v.astype(np.float32).astype(np.float64) for k, v in params.items()}
+    B = A @ rng.standard_normal((n, batch)) / np.sqrt(n)
+    B = np.ascontiguousarray(B.T)
+    Xt = np.ascontiguousarray((np.linalg.lstsq(A, B.T, rcond=None)[0]).T)
+    net = rebk.WarmStart(to_dev(A), in_dim, hidden, max_batch=batch)
+    net.set_params(params)
+    X0, Y = net.forward(to_dev(B), want_y=True)
+    ref = M.infer(params, B, A, out_scale=net.out_scale)
+    assert rel(Y.cpu().numpy(), ref["y"]) < 4 * HALF_ULP
+    assert rel(X0.cpu().numpy(), ref["x0"]) < 4 * HALF_ULP
+    loss = net.grad(to_dev(B), to_dev(Xt))
+    g = net.grads()
+    ref_loss, rg = M.loss_and_grads(params, B, A, Xt, round16=True, out_scale=net.out_scale)
+    assert abs(loss - ref_loss) < 8 * HALF_ULP * ref_loss
+    for k in M.PARAMS:
+        assert rel(g[k], rg[k]) < 8 * HALF_ULP, (k, rel(g[k], rg[k]))
+    net.adam(1e-3)
+    want = M.adam_step(params, {k: v.astype(np.float64) for k, v in g.items()}, {}, 1e-3)
+    got = net.params()
+    for k in M.PARAMS:
+        assert rel(got[k], want[k]) < 1e-6, k
+    net.close()
+
+
 def test_training_reduces_the_loss(rebk):
     """The targets are a linear function of the inputs (x = P b for a fixed P); 300 Adam steps."""
     rng = np.random.default_rng(3)

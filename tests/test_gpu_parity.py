@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2001_04179_amd import workloads as W
-from tests._helpers import gpu_vs_oracle, rel, to_dev
+from tests._helpers import RTOL_F64, gpu_vs_oracle, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -151,6 +151,59 @@ def test_low_precision_panels(rebk, oracle_lib, panel, kernel):
     assert np.array_equal(w_row, o_row) and np.array_equal(w_col, o_col)
     solver.close()
     gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=600, panel=panel, A_stored=A_stored)
+
+
+@pytest.mark.parametrize("panel", ["f64", "f32"])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_f32_caller_matrix(rebk, oracle_lib, panel, kernel):
+    """A handed over in FP32 (a_dtype F32): the panels hold its values widened exactly (FP64 panels)
+    or as they are (FP32 panels), so the oracle runs on the FP32 values in FP64."""
+    import torch
+    S = W.type2(400, 120, rng_seed=33, noise=0.1, row_tau=40, col_tau=12, seed=8)
+    A32 = S.A.astype(np.float32)
+    A_used = A32.astype(np.float64)
+    print(f"case f32 caller panels={panel} kernel={kernel}", flush=True)
+    solver = rebk.Solver(to_dev(A32, torch.float32), S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
+    w_row, w_col = solver.weights()
+    o_row, o_col = oracle_lib.block_weights(A_used, S.row_off, S.col_off)
+    assert np.array_equal(w_row, o_row) and np.array_equal(w_col, o_col)
+    out = solver.solve_ex(to_dev(S.b), max_iter=500, trace=True, kernel=kernel)
+    solver.close()
+    ref = oracle_lib.rebk_solve(A_used, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=500)
+    assert np.array_equal(out["j"].cpu().numpy(), ref["j"]) and np.array_equal(out["i"].cpu().numpy(), ref["i"])
+    assert rel(out["x"].cpu().numpy(), ref["x"]) <= RTOL_F64
+    assert rel(out["z"].cpu().numpy(), ref["z"]) <= RTOL_F64
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_zero_weight_blocks(rebk, oracle_lib, kernel):
+    """Blocks of zero Frobenius norm (a zero row block and two zero column blocks, one of them the
+    last): the device thresholds equal the oracle's, a zero-weight block is never drawn (Algorithm
+    1 draws blocks with probability proportional to their weight), the device draws equal the
+    oracle's bit for bit, and the solve matches the oracle."""
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((300, 90))
+    A[90:120, :] = 0.0           # row block 3 of 30-row blocks
+    A[:, 18:27] = 0.0            # column block 2 of 9-column blocks
+    A[:, 81:90] = 0.0            # the last column block
+    S = W.general(A, rng_seed=42, noise=0.1, row_tau=30, col_tau=9, seed=17)
+    print(f"case zero-weight blocks kernel={kernel}", flush=True)
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    w_row, w_col = solver.weights()
+    assert w_row[3] == 0.0 and w_col[2] == 0.0 and w_col[9] == 0.0
+    o_row, o_col = oracle_lib.block_weights(S.A, S.row_off, S.col_off)
+    assert np.array_equal(w_row, o_row) and np.array_equal(w_col, o_col)
+    T_row, T_col = solver.thresholds()
+    assert np.array_equal(T_row, oracle_lib.thresholds(o_row))
+    assert np.array_equal(T_col, oracle_lib.thresholds(o_col))
+    j, i = solver.sample_blocks(5, 100000, 3)
+    oj, oi = oracle_lib.sample_blocks(o_row, o_col, S.seed, 5, 100000, sys=3)
+    j, i = j.cpu().numpy(), i.cpu().numpy()
+    assert np.array_equal(j, oj) and np.array_equal(i, oi)
+    assert not np.any(i == 3) and not np.any(np.isin(j, [2, 9]))
+    assert set(np.unique(i)) == set(range(10)) - {3} and set(np.unique(j)) == set(range(10)) - {2, 9}
+    solver.close()
+    gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=400)
 
 
 def test_weights_and_thresholds_bit_equal(rebk, oracle_lib, cfg1):

@@ -110,3 +110,21 @@ def test_refined_invalid(rebk):
     with pytest.raises(ValueError):
         solver.solve_refined(to_dev(S.A.T.copy()), to_dev(S.b))
     solver.close()
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    return W.rank1200_2000x50000()
+
+
+@pytest.mark.parametrize("panel", ["bf16", "f16"])
+def test_refined_2000x50000_full_shape(rebk, oracle_lib, cfg3, panel):
+    """The mixed-precision workload at its real size and blocks (A = U V, 2000 x 50000, rank 1200;
+    20 row blocks of 100, 500 column blocks of 100), in the benchmark's launch configuration (the
+    whole-chip kernel): two outer steps of 50 inner iterations against the oracle on the same
+    stored panels."""
+    print(f"case 2000x50000 refined panels={panel}", flush=True)
+    out, ref = refined_pair(rebk, oracle_lib, cfg3, panel, inner=50, outer=2, kernel="grid")
+    assert out["result"].iterations == ref["iterations"] == 100
+    assert rel(out["x"].cpu().numpy(), ref["x"]) <= RTOL_F64, rel(out["x"].cpu().numpy(), ref["x"])
+    assert rel(out["z"].cpu().numpy(), ref["z"]) <= RTOL_F64, rel(out["z"].cpu().numpy(), ref["z"])

@@ -249,3 +249,16 @@ def test_invalid_inputs_rejected(oracle_lib):
         oracle_lib.rebk_solve(A, [0, 4], [0, 3], -1.0, 0, b, max_iter=3)
     with pytest.raises(ValueError):
         oracle_lib.rebk_solve(np.zeros((4, 3)), [0, 4], [0, 3], 1.0, 0, b, max_iter=3)
+
+
+def test_openmp_timing_variant_follows_the_oracle():
+    """The OpenMP variant used for the CPU timing baseline runs the same iterations (same draws)
+    as the plain oracle; only the summation of the z-step's column products is split over threads,
+    so the iterates agree to rounding."""
+    import oracle
+    S = W.factor_product(300, 90, 40, rng_seed=77, noise=0.1, row_tau=30, col_tau=9, seed=5)
+    ref = oracle.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=700, trace=False)
+    omp = oracle.rebk_solve_omp(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=700)
+    assert np.linalg.norm(omp["x"] - ref["x"]) <= 1e-12 * np.linalg.norm(ref["x"])
+    assert np.linalg.norm(omp["z"] - ref["z"]) <= 1e-12 * np.linalg.norm(ref["z"])
+    assert oracle.omp_threads() >= 1
