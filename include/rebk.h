@@ -161,6 +161,25 @@ int rebk_solve(rebk_handle_t h, const double *b_dev, const double *x0_dev, doubl
 int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t *opts, rebk_result_t *res);
 
 /*
+ * rebk_solve_ex for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, but the grid kernel's workspace (partial
+ * sums, reduced vectors, timeout flag) and the ||x_ref||^2 slot come from a
+ * static array the library holds on every device it runs on (4.25 MiB,
+ * room for up to 256 workgroups and blocks with max|I| + max|J| + 1 <= 512),
+ * cleared by a kernel at each call.  The caller passes inputs and outputs
+ * as for rebk_solve_ex.  Only the error (x_ref) and fixed-count stop rules
+ * are available: residual mode (x_ref NULL with tol > 0) returns
+ * REBK_ERR_INVALID, as does a system whose grid workspace exceeds the
+ * static array, or a current device other than the handle's.  Every call on
+ * a device shares that device's array and leaves the last call's contents
+ * in it: calls that overlap on one device (several streams or host threads)
+ * race and must be serialised by the caller.  Synchronizes the handle's
+ * stream.  Returns the solve status.
+ */
+int rebk_solve_ex_static(rebk_handle_t h, const rebk_solve_opts_t *opts, rebk_result_t *res);
+
+/*
  * Copy the FP64 block weights to host arrays w_row (s entries, ||A_{I_i,:}||_F^2)
  * and w_col (t entries, ||A_{:,J_j}||_F^2); either may be NULL.  Algorithm 1
  * (Section 2) draws column block j with probability ||A_{:,J_j}||_F^2 / ||A||_F^2

@@ -176,8 +176,10 @@ class Solver:
 
     def solve_ex(self, b: torch.Tensor, *, x0=None, z0=None, k0: int = 0, max_iter: int = 100000,
                  x_ref=None, tol: float = 0.0, check_every: int = 0, trace: bool = False,
-                 kernel: str = "auto", grid_wgs: int = 0, x_out=None, z_out=None):
-        """``rebk_solve_ex``.  Returns dict(x, z, result, j, i) (j, i: traces when requested)."""
+                 kernel: str = "auto", grid_wgs: int = 0, x_out=None, z_out=None, static_workspace: bool = False):
+        """``rebk_solve_ex`` (``rebk_solve_ex_static`` with static_workspace: the library allocates
+        nothing; pass x_out / z_out to allocate nothing here either).  Returns dict(x, z, result, j,
+        i) (j, i: traces when requested)."""
         x = x_out if x_out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
         z = z_out if z_out is not None else torch.empty(self.m, dtype=torch.float64, device=self.device)
         tj = ti = None
@@ -200,8 +202,9 @@ class Solver:
         o.kernel = N.KERNELS[kernel]
         o.grid_wgs = int(grid_wgs)
         res = N.Result()
-        code = N.load().rebk_solve_ex(self._h, ctypes.byref(o), ctypes.byref(res))
-        N.check(code, "rebk_solve_ex")
+        fn = "rebk_solve_ex_static" if static_workspace else "rebk_solve_ex"
+        code = getattr(N.load(), fn)(self._h, ctypes.byref(o), ctypes.byref(res))
+        N.check(code, fn)
         r = self._result(res)
         out = {"x": x, "z": z, "result": r}
         if trace:

@@ -66,6 +66,7 @@ SIGNATURES = {
     "rebk_destroy": (None, [P]),
     "rebk_solve": (ctypes.c_int, [P, P, P, P, F64, I64, ctypes.POINTER(Result)]),
     "rebk_solve_ex": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Result)]),
+    "rebk_solve_ex_static": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Result)]),
     "rebk_get_weights": (ctypes.c_int, [P, P, P]),
     "rebk_get_thresholds": (ctypes.c_int, [P, P, P]),
     "rebk_get_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 6),

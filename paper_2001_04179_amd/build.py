@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librebk.so")
 
-SOURCES = ["rebk_kernels.hip", "rebk_grid.hip", "rebk_batch.hip", "rebk_team.hip", "rebk_refine.hip", "rebk_beta.hip", "rebk_mlp.hip", "rebk_api.cpp"]
+SOURCES = ["rebk_kernels.hip", "rebk_grid.hip", "rebk_batch.hip", "rebk_team.hip", "rebk_refine.hip", "rebk_beta.hip", "rebk_mlp.hip", "rebk_static.hip", "rebk_api.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit (see DESIGN notes on the
 # build); the host pass warns that it does not know the feature, which is harmless.

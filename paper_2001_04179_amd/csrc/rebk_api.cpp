@@ -197,8 +197,16 @@ bool wg_fits(const rebk_handle* h, const rebk::SolveArgs& a) {
   return rebk::wg_solve_lds_bytes(a) <= 150 * 1024;
 }
 
+// Grid workspace handed in by the caller instead of the handle's: `words` words at `base`, cleared
+// with a fill kernel (no allocation, no memset node).
+struct FixedWorkspace {
+  unsigned long long* base;
+  size_t words;
+};
+
 // One call of the iteration kernel for iterations k0+1 .. k0+iters.
-int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, int* used_kernel) {
+int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, int* used_kernel,
+                   const FixedWorkspace* fixed = nullptr) {
   if (kernel == REBK_KERNEL_AUTO) {
     // One workgroup wins only for tiny systems: per iteration it walks both blocks and all of z
     // and x.  Measured on MI355X: 5.7 us vs 7.3 us (whole chip) at 250 x 120 with 10 x 10 blocks,
@@ -235,15 +243,27 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   gs.stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
   const size_t part_words = (size_t)2 * G * gs.stride * 2;
   const size_t gsum_words = (size_t)rebk::kGridSumRing * rebk::kGridSumCopies * gs.stride * 2;
-  int rc = ensure_grid_workspace(h, part_words, gsum_words);
-  if (rc != REBK_OK) return rc;
-  gs.part = h->part;
-  gs.gsum = h->gsum;
-  gs.timeout = h->timeout;
-  // epochs restart at 1 every launch: clear every tag of the previous launch
-  HIP_TRY(hipMemsetAsync(h->part, 0, part_words * sizeof(unsigned long long), h->stream));
-  HIP_TRY(hipMemsetAsync(h->gsum, 0, gsum_words * sizeof(unsigned long long), h->stream));
-  HIP_TRY(hipMemsetAsync(h->timeout, 0, sizeof(int), h->stream));
+  if (fixed) {
+    // part, gsum and the timeout flag (one 256-byte line) carved from the given words, then cleared
+    const size_t need = part_words + gsum_words + 32;
+    if (need > fixed->words)
+      return fail(REBK_ERR_INVALID, "the grid kernel needs %zu workspace words here; the static workspace holds %zu",
+                  need, fixed->words);
+    gs.part = fixed->base;
+    gs.gsum = fixed->base + part_words;
+    gs.timeout = (int*)(fixed->base + part_words + gsum_words);
+    HIP_TRY(rebk::launch_fill_zero(fixed->base, need, h->stream));
+  } else {
+    int rc = ensure_grid_workspace(h, part_words, gsum_words);
+    if (rc != REBK_OK) return rc;
+    gs.part = h->part;
+    gs.gsum = h->gsum;
+    gs.timeout = h->timeout;
+    // epochs restart at 1 every launch: clear every tag of the previous launch
+    HIP_TRY(hipMemsetAsync(h->part, 0, part_words * sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipMemsetAsync(h->gsum, 0, gsum_words * sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipMemsetAsync(h->timeout, 0, sizeof(int), h->stream));
+  }
   HIP_TRY(rebk::launch_grid_solve(a, gs, h->panel_dtype, G, row_lds, h->stream));
   return REBK_OK;
 }
@@ -577,6 +597,72 @@ int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_result_t* re
   }
   r.kernel = used;
   r.time_ms = ms_total;
+  if (res) *res = r;
+  return r.status;
+}
+
+int rebk_solve_ex_static(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_result_t* res) {
+  g_err[0] = 0;
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  if (!o) return fail(REBK_ERR_INVALID, "opts is NULL");
+  if (!o->b_dev || !o->x_out_dev) return fail(REBK_ERR_INVALID, "b and x_out are required");
+  if (o->max_iter <= 0) return fail(REBK_ERR_INVALID, "max_iter must be positive");
+  if (o->k0 < 0) return fail(REBK_ERR_INVALID, "k0 must be non-negative");
+  if (o->check_every < 0) return fail(REBK_ERR_INVALID, "check_every must be non-negative");
+  if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
+  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel");
+  if (!o->x_ref_dev && o->tol > 0.0)
+    return fail(REBK_ERR_INVALID, "the residual stop rule is not available without allocation; give x_ref or tol <= 0");
+  if ((o->trace_j_dev == nullptr) != (o->trace_i_dev == nullptr))
+    return fail(REBK_ERR_INVALID, "give both trace buffers or none");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != h->device) return fail(REBK_ERR_INVALID, "the handle's device (%d) is not the current device (%d)", h->device, dev);
+  unsigned long long* ws = nullptr;
+  HIP_TRY(rebk::static_scratch(dev, &ws));
+  // the last 32 words hold ||x_ref||^2; the rest is the grid workspace
+  const FixedWorkspace fixed{ws, rebk::kStaticScratchWords - 32};
+  double* xr2_dev = (double*)(ws + rebk::kStaticScratchWords - 32);
+
+  rebk::SolveArgs a = base_args(h);
+  a.b = o->b_dev;
+  a.x_in = o->x0_dev;
+  a.z_in = o->z0_dev;
+  a.x_out = o->x_out_dev;
+  a.z_out = o->z_out_dev;
+  a.x_ref = o->x_ref_dev;
+  a.tol = o->tol;
+  a.k0 = o->k0;
+  a.trace_j = o->trace_j_dev;
+  a.trace_i = o->trace_i_dev;
+  a.max_iter = o->max_iter;
+  a.check_every = o->check_every > 0 ? o->check_every : 1;
+  if (a.x_ref) {
+    double xr2 = 0.0;
+    HIP_TRY(rebk::launch_sumsq_in_order(o->x_ref_dev, h->n, xr2_dev, h->stream));
+    HIP_TRY(hipMemcpyAsync(&xr2, xr2_dev, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (!(xr2 > 0.0) || !std::isfinite(xr2)) return fail(REBK_ERR_INVALID, "x_ref must be non-zero and finite");
+    a.xref_sq = xr2;
+  }
+  rebk_result_t r{};
+  r.rel_err = -1.0;
+  int used = 0;
+  float ms = 0.0f;
+  HIP_TRY(hipEventRecord(h->ev0, h->stream));
+  int rc = run_iterations(h, a, o->kernel, o->grid_wgs, &used, &fixed);
+  if (rc != REBK_OK) return rc;
+  HIP_TRY(hipEventRecord(h->ev1, h->stream));
+  rebk::DevStatus ds{};
+  HIP_TRY(hipMemcpyAsync(&ds, h->status_d, sizeof(ds), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (ds.status == REBK_ERR_TIMEOUT) return fail(REBK_ERR_TIMEOUT, "grid barrier spin limit exceeded");
+  r.status = a.x_ref ? ds.status : REBK_OK;
+  r.iterations = ds.last_k - o->k0;
+  if (a.x_ref && ds.err2 >= 0.0) r.rel_err = std::sqrt(ds.err2) / std::sqrt(a.xref_sq);
+  r.kernel = used;
+  r.time_ms = ms;
   if (res) *res = r;
   return r.status;
 }

@@ -61,6 +61,20 @@ struct GridSync {
   int32_t stride;            // entries per vector (>= max_nJ + max_nI + 1, a multiple of 32)
 };
 
+// Static workspace of rebk_solve_ex_static (rebk_static.hip): room for the grid workspace of up to
+// kStaticMaxGrid workgroups and a reduction stride of kStaticMaxStride entries, plus 64 words for
+// the timeout flag and ||x_ref||^2.  4.25 MiB per device.
+constexpr int kStaticMaxGrid = 256;
+constexpr int kStaticMaxStride = 512;
+constexpr size_t kStaticScratchWords = (size_t)2 * kStaticMaxGrid * kStaticMaxStride * 2 +
+                                       (size_t)kGridSumRing * kGridSumCopies * kStaticMaxStride * 2 + 64;
+// Address of this device's static workspace (kStaticScratchWords words), looked up once per device
+// with that device current.
+hipError_t static_scratch(int device, unsigned long long** ptr);
+hipError_t launch_fill_zero(unsigned long long* p, size_t n, hipStream_t st);
+// *out = sum of v[q]^2 in index order (one thread; the same value as a sequential host loop)
+hipError_t launch_sumsq_in_order(const double* v, int64_t n, double* out, hipStream_t st);
+
 // One system of a batch: its panels, tables and Philox stream (device copy of the handle's data).
 struct BatchSys {
   const void* Arow;          // row panels, as in SolveArgs

@@ -56,6 +56,7 @@ def test_host_validation_without_device():
     assert lib.rebk_create(ctypes.byref(h), fake, 2, 0, 10, 4, 4, ro, 2, co, 1, 1.0, 0, None) == N.ERR_INVALID
     # NULL handle everywhere
     assert lib.rebk_solve_ex(None, None, None) == N.ERR_INVALID
+    assert lib.rebk_solve_ex_static(None, None, None) == N.ERR_INVALID
     assert lib.rebk_get_weights(None, None, None) == N.ERR_INVALID
     lib.rebk_destroy(None)
 
