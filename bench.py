@@ -82,8 +82,8 @@ def parse():
                    help="inner iterations per refinement step to try")
     p.add_argument("--batch-panels", default="f32", choices=["f64", "f32", "bf16", "f16"])
     p.add_argument("--batch-count", type=int, default=256)
-    p.add_argument("--batch-plain-sample", type=int, default=8,
-                   help="systems whose first right-hand side is also solved alone with FP64 panels")
+    p.add_argument("--no-plain", action="store_true",
+                   help="batched: skip the plain FP64 comparison (profiling runs)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", TRAFFIC_FILE),
@@ -321,7 +321,7 @@ def run_batched(args, steps, warmup, with_cpu):
     # batch's check cadence; a system's total is that time times its right-hand sides
     plain_s, plain_its = [], []
     t_plain0 = time.perf_counter()
-    for sidx, S in enumerate(systems):
+    for sidx, S in enumerate([] if args.no_plain else systems):
         A_d = torch.from_numpy(S.A).to(dev)
         sv = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, 0, panel_dtype="f64")
         del A_d
@@ -334,7 +334,7 @@ def run_batched(args, steps, warmup, with_cpu):
         plain_its.append(o["result"].iterations)
         sv.close()
     t_plain = time.perf_counter() - t_plain0
-    plain_total = float(np.sum(plain_s))
+    plain_total = float(np.sum(plain_s)) if plain_s else float("nan")
     step_s = wall / steps
     res = {
         "value": nrhs_total / step_s,
@@ -351,11 +351,12 @@ def run_batched(args, steps, warmup, with_cpu):
                        "max": int(out["iterations"].max()), "sum": int(out["iterations"].sum())},
         "rel_err_max": float(max(errs)),
         "kernel_ms": kernel_ms,
-        "plain_f64": {"seconds_est": plain_total, "solves_per_s_est": nrhs_total / plain_total,
-                      "how": "plain FP64 REBK, one right-hand side at a time with check_every 16: the first "
-                             "right-hand side of every system timed alone, times the system's right-hand sides",
-                      "iterations_sum_first_rhs": int(np.sum(plain_its)), "measured_seconds": t_plain},
-        "speedup_vs_plain_f64": plain_total / step_s,
+        "plain_f64": None if not plain_s else {
+            "seconds_est": plain_total, "solves_per_s_est": nrhs_total / plain_total,
+            "how": "plain FP64 REBK, one right-hand side at a time with check_every 16: the first "
+                   "right-hand side of every system timed alone, times the system's right-hand sides",
+            "iterations_sum_first_rhs": int(np.sum(plain_its)), "measured_seconds": t_plain},
+        "speedup_vs_plain_f64": (plain_total / step_s) if plain_s else None,
         "prep_seconds": {"generate": t_gen, "create": t_create, "autotune": t_tune},
         # per system: rows, columns, rank (null: full), tile width, most iterations of a right-hand side
         "per_system": per_system,

@@ -75,8 +75,8 @@ def _close_all():
                 pass
 
 
-def _finalize(obj):
-    if sys.is_finalizing():
+def _finalize(obj, _is_finalizing=sys.is_finalizing):
+    if _is_finalizing():
         return
     try:
         obj.close()
@@ -124,8 +124,8 @@ class Solver:
             N.load().rebk_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):  # bound at definition: module globals are gone at shutdown
+        _fin(self)
 
     def __enter__(self):
         return self
@@ -291,8 +291,8 @@ class Batch:
             N.load().rebk_batch_destroy(self._b)
             self._b = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):  # bound at definition: module globals are gone at shutdown
+        _fin(self)
 
     def _opts(self, B, x_ref, x0, x_out, z_out, max_iter, tol, check_every, threads, lds_budget, max_tile,
               xcd_order, z0_from_x0=False, team=0):
@@ -415,8 +415,8 @@ class WarmStart:
             N.load().rebk_mlp_destroy(self._w)
             self._w = ctypes.c_void_p()
 
-    def __del__(self):
-        _finalize(self)
+    def __del__(self, _fin=_finalize):  # bound at definition: module globals are gone at shutdown
+        _fin(self)
 
     def set_params(self, params: dict):
         arrs = [np.ascontiguousarray(params[k], dtype=np.float32) if k in params else None for k in self.NAMES]
