@@ -81,9 +81,20 @@ typedef enum {
 typedef enum {
     REBK_KERNEL_AUTO = 0,     /* WORKGROUP for tiny systems (m |J| + |I| n + 4 (m + n) <= 8192), GRID otherwise */
     REBK_KERNEL_WORKGROUP = 1,/* one workgroup runs the whole solve (small systems) */
-    REBK_KERNEL_GRID = 2      /* one persistent cooperative grid, one grid-wide reduction per
+    REBK_KERNEL_GRID = 2,     /* one persistent cooperative grid, one grid-wide reduction per
                                  iteration; needs ceil(n / grid) + 8 <= 256 owned columns, blocks
                                  of at most 256 columns and its slabs within 160 KB of LDS */
+    REBK_KERNEL_PIPE = 3      /* the grid kernel pipelined over three iterations: the same
+                                 iterates of Algorithm 1 (Section 2), the next steps' block
+                                 products formed from x and z two and three iterations old and
+                                 corrected with the Gram matrices A A^T and A^T A, so only one
+                                 grid-wide broadcast per iteration is on the critical path.  Builds
+                                 A A^T, A^T A and a row-major copy of A in FP64 on first use
+                                 (8 (m^2 + n^2 + m n) bytes, kept until rebk_destroy or
+                                 rebk_pipe_release; see rebk_pipe_prepare).  Same limits as GRID,
+                                 plus max|I| + max|J| + 1 <= the grid size and <= 256 (after
+                                 rounding up to a multiple of 32); no refinement steps
+                                 (rebk_solve_refined) */
 } rebk_kernel_t;
 
 typedef struct {
@@ -170,14 +181,29 @@ int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t *opts, rebk_result_t 
  * cleared by a kernel at each call.  The caller passes inputs and outputs
  * as for rebk_solve_ex.  Only the error (x_ref) and fixed-count stop rules
  * are available: residual mode (x_ref NULL with tol > 0) returns
- * REBK_ERR_INVALID, as does a system whose grid workspace exceeds the
- * static array, or a current device other than the handle's.  Every call on
+ * REBK_ERR_INVALID, as does REBK_KERNEL_PIPE, a system whose grid workspace
+ * exceeds the static array, or a current device other than the handle's.  Every call on
  * a device shares that device's array and leaves the last call's contents
  * in it: calls that overlap on one device (several streams or host threads)
  * race and must be serialised by the caller.  Synchronizes the handle's
  * stream.  Returns the solve status.
  */
 int rebk_solve_ex_static(rebk_handle_t h, const rebk_solve_opts_t *opts, rebk_result_t *res);
+
+/*
+ * Build now what REBK_KERNEL_PIPE needs (A A^T, A^T A and a row-major copy of
+ * A, FP64 from the stored panel values, 8 (m^2 + n^2 + m n) bytes of device
+ * memory); otherwise the first pipelined solve builds them, before its timed
+ * region.  The products run through rocBLAS dgemm on the handle's stream.
+ * build_ms (host, may be NULL) receives the build time in milliseconds (0 if
+ * they were already built).  Synchronizes the handle's stream.  Errors:
+ * REBK_ERR_INVALID for a NULL handle, REBK_ERR_OOM when the memory is not
+ * available, REBK_ERR_HIP for a failed product.
+ */
+int rebk_pipe_prepare(rebk_handle_t h, double *build_ms);
+
+/* Free what rebk_pipe_prepare built (NULL or nothing built is ignored). */
+void rebk_pipe_release(rebk_handle_t h);
 
 /*
  * Copy the FP64 block weights to host arrays w_row (s entries, ||A_{I_i,:}||_F^2)

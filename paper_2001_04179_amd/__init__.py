@@ -124,6 +124,17 @@ class Solver:
             N.load().rebk_destroy(self._h)
             self._h = ctypes.c_void_p()
 
+    def pipe_prepare(self) -> float:
+        """``rebk_pipe_prepare``: build the pipelined kernel's Gram matrices now; returns the build
+        time in ms (0 when already built)."""
+        ms = ctypes.c_double(0.0)
+        N.check(N.load().rebk_pipe_prepare(self._h, ctypes.byref(ms)), "rebk_pipe_prepare")
+        return ms.value
+
+    def pipe_release(self):
+        """``rebk_pipe_release``: free the pipelined kernel's Gram matrices."""
+        N.load().rebk_pipe_release(self._h)
+
     def __del__(self, _fin=_finalize):  # bound at definition: module globals are gone at shutdown
         _fin(self)
 

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "diverged", -1: "invalid", -2: "
                 -4: "timeout"}
 
 # rebk_kernel_t
-KERNELS = {"auto": 0, "workgroup": 1, "grid": 2}
+KERNELS = {"auto": 0, "workgroup": 1, "grid": 2, "pipe": 3}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 
@@ -67,6 +67,8 @@ SIGNATURES = {
     "rebk_solve": (ctypes.c_int, [P, P, P, P, F64, I64, ctypes.POINTER(Result)]),
     "rebk_solve_ex": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Result)]),
     "rebk_solve_ex_static": (ctypes.c_int, [P, ctypes.POINTER(SolveOpts), ctypes.POINTER(Result)]),
+    "rebk_pipe_prepare": (ctypes.c_int, [P, ctypes.POINTER(F64)]),
+    "rebk_pipe_release": (None, [P]),
     "rebk_get_weights": (ctypes.c_int, [P, P, P]),
     "rebk_get_thresholds": (ctypes.c_int, [P, P, P]),
     "rebk_get_info": (ctypes.c_int, [P] + [ctypes.POINTER(I64)] * 6),

@@ -25,6 +25,10 @@ HIPCC_FLAGS = [
 ]
 
 
+# rocBLAS builds the Gram matrices of the pipelined kernel (plain FP64 GEMMs)
+LINK_FLAGS = ["-L" + os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"), "-lrocblas"]
+
+
 def hipcc() -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     cand = os.path.join(rocm, "bin", "hipcc")
@@ -35,7 +39,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source into ``paper_2001_04179_amd/librebk.so`` (always recompiles)."""
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I" + INCLUDE, "-I" + CSRC, "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+           *[os.path.join(CSRC, s) for s in SOURCES], *LINK_FLAGS]
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,8 +1,10 @@
 // Host runtime of librebk.so: argument validation, device memory, sampling tables and the
 // solve drivers behind the C ABI declared in include/rebk.h.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -104,6 +106,16 @@ struct rebk_handle {
   size_t part_cap = 0;
   size_t gsum_cap = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // pipelined kernel: A A^T (m x m), A^T A (n x n), A row-major (m x n), FP64
+  double* pipe_G = nullptr;
+  double* pipe_H = nullptr;
+  double* pipe_Arm = nullptr;
+
+  void release_pipe() {
+    dfree(pipe_G);
+    dfree(pipe_H);
+    dfree(pipe_Arm);
+  }
 
   ~rebk_handle() {
     dfree(Arow);
@@ -119,6 +131,7 @@ struct rebk_handle {
     dfree(part);
     dfree(gsum);
     dfree(timeout);
+    release_pipe();
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
   }
@@ -197,6 +210,54 @@ bool wg_fits(const rebk_handle* h, const rebk::SolveArgs& a) {
   return rebk::wg_solve_lds_bytes(a) <= 150 * 1024;
 }
 
+// The pipelined kernel's FP64 operands: A row-major from the row panels, then G = A A^T and
+// H = A^T A with rocBLAS (the row-major A is the column-major n x m matrix X = A^T, so
+// G = X^T X and H = X X^T).  *ms: build time (0 when already built).
+int ensure_pipe(rebk_handle* h, double* ms) {
+  if (ms) *ms = 0.0;
+  if (h->pipe_G) return REBK_OK;
+  const int64_t m = h->m, n = h->n;
+  if (m > INT32_MAX || n > INT32_MAX) return fail(REBK_ERR_INVALID, "pipelined kernel: dimensions beyond 32 bits");
+  const size_t bytes = 8 * ((size_t)m * m + (size_t)n * n + (size_t)m * n);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  if (bytes + ((size_t)1 << 30) > free_b)
+    return fail(REBK_ERR_OOM, "pipelined kernel: %zu bytes of Gram matrices exceed free memory (%zu)", bytes, free_b);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (hipMalloc((void**)&h->pipe_Arm, 8 * (size_t)m * n) != hipSuccess ||
+      hipMalloc((void**)&h->pipe_G, 8 * (size_t)m * m) != hipSuccess ||
+      hipMalloc((void**)&h->pipe_H, 8 * (size_t)n * n) != hipSuccess) {
+    h->release_pipe();
+    return fail(REBK_ERR_OOM, "pipelined kernel: cannot allocate %zu bytes", bytes);
+  }
+  hipError_t e = rebk::launch_unpack_rows(h->Arow, h->panel_dtype, n, h->row_off_d, (int32_t)h->s, h->pipe_Arm,
+                                          h->stream);
+  if (e != hipSuccess) {
+    h->release_pipe();
+    return fail(REBK_ERR_HIP, "unpack of A: %s", hipGetErrorString(e));
+  }
+  rocblas_handle bh = nullptr;
+  rocblas_status bs = rocblas_create_handle(&bh);
+  if (bs == rocblas_status_success) bs = rocblas_set_stream(bh, h->stream);
+  if (bs == rocblas_status_success) bs = rocblas_set_atomics_mode(bh, rocblas_atomics_not_allowed);  // reproducible
+  const double one = 1.0, zero = 0.0;
+  const rocblas_int M = (rocblas_int)m, N = (rocblas_int)n;
+  if (bs == rocblas_status_success)
+    bs = rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, M, M, N, &one, h->pipe_Arm, N,
+                       h->pipe_Arm, N, &zero, h->pipe_G, M);
+  if (bs == rocblas_status_success)
+    bs = rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_transpose, N, N, M, &one, h->pipe_Arm, N,
+                       h->pipe_Arm, N, &zero, h->pipe_H, N);
+  e = hipStreamSynchronize(h->stream);
+  if (bh) (void)rocblas_destroy_handle(bh);
+  if (bs != rocblas_status_success || e != hipSuccess) {
+    h->release_pipe();
+    return fail(REBK_ERR_HIP, "Gram products: rocBLAS status %d, %s", (int)bs, hipGetErrorString(e));
+  }
+  if (ms) ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return REBK_OK;
+}
+
 // Grid workspace handed in by the caller instead of the handle's: `words` words at `base`, cleared
 // with a fill kernel (no allocation, no memset node).
 struct FixedWorkspace {
@@ -218,6 +279,42 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   if (kernel == REBK_KERNEL_WORKGROUP) {
     if (!wg_fits(h, a)) return fail(REBK_ERR_INVALID, "system too large for the one-workgroup kernel");
     HIP_TRY(rebk::launch_wg_solve(a, h->panel_dtype, rebk::kWgThreads, rebk::wg_solve_lds_bytes(a), h->stream));
+    return REBK_OK;
+  }
+  if (kernel == REBK_KERNEL_PIPE) {
+    if (fixed) return fail(REBK_ERR_INVALID, "the pipelined kernel needs allocated memory; use GRID here");
+    if (a.g || a.y_out) return fail(REBK_ERR_INVALID, "the pipelined kernel runs no refinement steps");
+    const int G = grid_wgs > 0 ? grid_wgs : h->cus;
+    if (G > 1024) return fail(REBK_ERR_INVALID, "at most 1024 workgroups in the pipelined kernel");
+    rebk::GridSync gs{};
+    gs.stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
+    if (gs.stride > G || gs.stride > rebk::kPipeMaxStride)
+      return fail(REBK_ERR_INVALID,
+                  "pipelined kernel: %d broadcast entries need as many workgroups (grid %d) and at most %d",
+                  gs.stride, G, rebk::kPipeMaxStride);
+    if ((h->n + G - 1) / G + 8 > rebk::kGridThreads)
+      return fail(REBK_ERR_INVALID, "too many columns per workgroup; use a larger grid");
+    if (h->max_nJ > rebk::kGridThreads)
+      return fail(REBK_ERR_INVALID, "column blocks wider than %d columns need the one-workgroup kernel", rebk::kGridThreads);
+    const size_t lds = rebk::pipe_solve_lds_bytes(a, G, gs.stride, h->panel_dtype);
+    if (lds > 150 * 1024) return fail(REBK_ERR_INVALID, "pipelined kernel needs %zu bytes of LDS per workgroup", lds);
+    int per_cu = 0;
+    HIP_TRY(rebk::pipe_solve_max_blocks(h->panel_dtype, lds, &per_cu));
+    if (per_cu <= 0 || G > per_cu * h->cus)
+      return fail(REBK_ERR_INVALID, "grid of %d workgroups cannot be co-resident (%d per CU)", G, per_cu);
+    int rc = ensure_pipe(h, nullptr);
+    if (rc != REBK_OK) return rc;
+    const size_t part_words = (size_t)4 * G * gs.stride * 2;
+    const size_t gsum_words = (size_t)rebk::kGridSumRing * rebk::kGridSumCopies * gs.stride * 2;
+    rc = ensure_grid_workspace(h, part_words, gsum_words);
+    if (rc != REBK_OK) return rc;
+    gs.part = h->part;
+    gs.gsum = h->gsum;
+    gs.timeout = h->timeout;
+    HIP_TRY(hipMemsetAsync(h->part, 0, part_words * sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipMemsetAsync(h->gsum, 0, gsum_words * sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipMemsetAsync(h->timeout, 0, sizeof(int), h->stream));
+    HIP_TRY(rebk::launch_pipe_solve(a, gs, h->pipe_G, h->pipe_H, h->pipe_Arm, h->panel_dtype, G, h->stream));
     return REBK_OK;
   }
   if (kernel != REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel %d", kernel);
@@ -485,7 +582,7 @@ int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_result_t* re
   if (o->k0 < 0) return fail(REBK_ERR_INVALID, "k0 must be non-negative");
   if (o->check_every < 0) return fail(REBK_ERR_INVALID, "check_every must be non-negative");
   if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
-  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel");
+  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_PIPE) return fail(REBK_ERR_INVALID, "unknown kernel");
   const bool ref_mode = o->x_ref_dev != nullptr;
   const bool residual_mode = !ref_mode && o->tol > 0.0;
   rebk::SolveArgs a = base_args(h);
@@ -510,6 +607,11 @@ int rebk_solve_ex(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_result_t* re
     for (double v : xr) xr2 += v * v;
     if (!(xr2 > 0.0) || !std::isfinite(xr2)) return fail(REBK_ERR_INVALID, "x_ref must be non-zero and finite");
     a.xref_sq = xr2;
+  }
+
+  if (o->kernel == REBK_KERNEL_PIPE) {  // the Gram matrices are built outside the timed region
+    int rc = ensure_pipe(h, nullptr);
+    if (rc != REBK_OK) return rc;
   }
 
   rebk_result_t r{};
@@ -610,7 +712,7 @@ int rebk_solve_ex_static(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_resul
   if (o->k0 < 0) return fail(REBK_ERR_INVALID, "k0 must be non-negative");
   if (o->check_every < 0) return fail(REBK_ERR_INVALID, "check_every must be non-negative");
   if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
-  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel");
+  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_PIPE) return fail(REBK_ERR_INVALID, "unknown kernel");
   if (!o->x_ref_dev && o->tol > 0.0)
     return fail(REBK_ERR_INVALID, "the residual stop rule is not available without allocation; give x_ref or tol <= 0");
   if ((o->trace_j_dev == nullptr) != (o->trace_i_dev == nullptr))
@@ -665,6 +767,17 @@ int rebk_solve_ex_static(rebk_handle_t h, const rebk_solve_opts_t* o, rebk_resul
   r.time_ms = ms;
   if (res) *res = r;
   return r.status;
+}
+
+int rebk_pipe_prepare(rebk_handle_t h, double* build_ms) {
+  g_err[0] = 0;
+  if (build_ms) *build_ms = 0.0;
+  if (!h) return fail(REBK_ERR_INVALID, "handle is NULL");
+  return ensure_pipe(h, build_ms);
+}
+
+void rebk_pipe_release(rebk_handle_t h) {
+  if (h) h->release_pipe();
 }
 
 int rebk_solve(rebk_handle_t h, const double* b_dev, const double* x0_dev, double* x_out_dev, double tol,
@@ -1346,7 +1459,7 @@ extern "C" int rebk_solve_refined(rebk_handle_t h, const rebk_refine_opts_t* o, 
   if (o->inner_iters <= 0) return fail(REBK_ERR_INVALID, "inner_iters must be positive");
   if (o->max_outer < 0) return fail(REBK_ERR_INVALID, "max_outer must be non-negative");
   if (!(o->tol == o->tol)) return fail(REBK_ERR_INVALID, "tol is NaN");
-  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_GRID) return fail(REBK_ERR_INVALID, "unknown kernel");
+  if (o->kernel < REBK_KERNEL_AUTO || o->kernel > REBK_KERNEL_PIPE) return fail(REBK_ERR_INVALID, "unknown kernel");
   const int64_t m = h->m, n = h->n;
   hipStream_t st = h->stream;
   DevBuffers buf;

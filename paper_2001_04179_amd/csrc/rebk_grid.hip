@@ -88,6 +88,9 @@ __device__ __forceinline__ double tag_value(unsigned long long w0, unsigned long
 // Wait until every memory operation this wave issued has completed (including copies into LDS);
 // the memory clobber keeps the compiler from moving accesses across.
 __device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Workgroup barrier that waits only for this wave's LDS operations: copies into LDS still in
+// flight keep going (their waves wait for them with wait_mem before the data is read).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 struct GridLayout {
   int NR, NC;     // max rows / columns owned by one workgroup
@@ -713,6 +716,748 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Pipelined whole-chip kernel: one broadcast hop per iteration on the critical path.
+//
+// The x-step of iteration t needs A_{I_t} x^{t-1}, and x^{t-1} = x^{t-3} - c_{t-2} A_{I_{t-2}}^T u^{t-2}
+// - c_{t-1} A_{I_{t-1}}^T u^{t-1}, so
+//   u^t = [A_{I_t} x^{t-3} - b_{I_t} + z^{t-2}_{I_t}] - c_{t-2} G_{I_t,I_{t-2}} u^{t-2} - c_{t-1} G_{I_t,I_{t-1}} u^{t-1}
+//         - c'_{t-1} A_{I_t,J_{t-1}} v^{t-1} - c'_t A_{I_t,J_t} v^t,
+// and likewise v^{t+1} = [A_{J_{t+1}}^T z^{t-2}] - c'_{t-1} H_{J_{t+1},J_{t-1}} v^{t-1} - c'_t H_{J_{t+1},J_t} v^t,
+// with G = A A^T and H = A^T A (FP64, in HBM) and c, c' the row and column step coefficients.  The
+// iterates are Algorithm 1's; only the order of the sums differs from the oracle's.
+//
+// Round t broadcasts B^t = (v^{t+1}, u^t) (and, when a check is due, ||x^{t-3} - x_ref||^2), one
+// entry per owning workgroup.  An entry is P^t (the bracket, summed over workgroups: partial sums
+// of state two and three iterations old) minus w'_t . B^{t-2} minus w_t . B^{t-1}, where w'_t and
+// w_t are the scaled rows of H, G and A above, laid out like B.  Wave 0 of the owner holds w_t and
+// w'_{t+1} in registers; as soon as it has polled B^{t-1} it forms its entry of B^t and publishes
+// it, with no workgroup barrier in between, then hands B^{t-1} to waves 1..3.  Those waves, one
+// round behind, update z and x, publish the partial sums of round t + 2, gather the owner's sum of
+// round t + 1 and stage the slabs and rows of later rounds through registers.
+constexpr int kPipeSlabs = 5;   // slab buffers of each kind (a slab is read in two rounds three apart)
+constexpr int kPipeParts = 4;   // partial vectors kept per workgroup (round t in slot t & 3)
+constexpr int kPipeStage = 32;  // dwords a helper lane holds in flight per round (the rest: direct copies)
+static_assert(kPipeMaxStride == 256, "wave 0 holds a broadcast vector in 8 registers per lane pair");
+
+struct PipeLayout {
+  int NR, NC;
+  int NRS;        // LDS run length of a column-slab run (owned rows rounded up to 16 bytes)
+  size_t dbl;     // doubles before the slabs
+  size_t slabC, slabR;
+};
+
+__host__ __device__ inline PipeLayout pipe_layout(int64_t m, int64_t n, int MI, int MJ, int E, int G, int esz) {
+  PipeLayout L;
+  L.NR = (int)((m + G - 1) / G) + 16 / esz;
+  L.NC = (int)((n + G - 1) / G) + kColOwnAlign;
+  L.NRS = L.NR + 16 / esz;
+  // z history (4 NR), b (NR), x history (4 NC), x_ref (NC), three broadcast vectors, raw rows of
+  // w_t and w'_t (two of each), two gathered sums; an even count keeps the slabs 16-byte aligned
+  L.dbl = (5 * (size_t)L.NR + 5 * (size_t)L.NC + 7 * (size_t)E + 2 + 1) & ~(size_t)1;
+  L.slabC = ((size_t)L.NRS * MJ + 7) / 8 * 8;
+  L.slabR = ((size_t)L.NC * MI + 7) / 8 * 8;
+  return L;
+}
+
+using gdword = const __attribute__((address_space(1))) uint32_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+using gdword4 = const __attribute__((address_space(1))) u32x4;
+using gdouble = const __attribute__((address_space(1))) double;
+
+template <typename TP>
+__global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, GridSync gs,
+                                                                  const double* __restrict__ Gm,
+                                                                  const double* __restrict__ Hm,
+                                                                  const double* __restrict__ Arm) {
+  extern __shared__ double lds[];
+  __shared__ int s_j[kRing], s_i[kRing], s_nJ[kRing], s_nI[kRing];
+  __shared__ int64_t s_c0[kRing], s_r0[kRing];
+  __shared__ double s_cc[kRing], s_cr[kRing];
+  __shared__ int s_ok;
+  __shared__ int s_zflag;  // z^t of the owned rows is in LDS for t <= s_zflag
+  __shared__ int s_gflag;  // the owner's gathered sum of round t is in LDS for t <= s_gflag
+  const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x, T = blockDim.x, lane = tid & 63;
+  const int64_t m = a.m, n = a.n;
+  const int MJ = a.max_nJ, MI = a.max_nI, E = gs.stride;
+  const int esz = (int)sizeof(TP);
+  const PipeLayout L = pipe_layout(m, n, MI, MJ, E, G, esz);
+  const int ra = 16 / esz;
+  const int64_t r0 = own_lo(w, m, G, ra), r1 = own_lo(w + 1, m, G, ra);
+  const int64_t cA = own_lo(w, n, G, kColOwnAlign), cB = own_lo(w + 1, n, G, kColOwnAlign);
+  const int nr = (int)(r1 - r0), nc = (int)(cB - cA);
+  const int c16 = (nr * esz + 15) / 16;  // 16-byte chunks of one column-slab run
+  const int nrs = c16 * 16 / esz;        // its length in LDS (>= nr)
+
+  double* zh = lds;               // z^t on owned rows at zh + (t & 3) NR
+  double* bl = zh + 4 * L.NR;     // b on owned rows
+  double* xh = bl + L.NR;         // x^t on owned columns at xh + (t & 3) NC
+  double* xr = xh + 4 * L.NC;     // x_ref on owned columns
+  double* bv = xr + L.NC;         // B^t at bv + (t % 3) E
+  double* wr = bv + 3 * E;        // raw rows of w_t at wr + (t & 1) E (v part at 0, u part at MJ)
+  double* wpr = wr + 2 * E;       // raw rows of w'_t at wpr + (t & 1) E
+  double* gat = wpr + 2 * E;      // gathered sum of round t at gat[t & 1]
+  TP* slabC = (TP*)(lds + L.dbl); // column slab of J_t at slabC + (t % 5) slabC (runs of nrs)
+  TP* slabR = slabC + kPipeSlabs * L.slabC;
+
+  const TP* __restrict__ Arow = (const TP*)a.Arow;
+  const TP* __restrict__ Acol = (const TP*)a.Acol;
+  const int64_t K = a.max_iter;
+  const int64_t ce = a.check_every > 0 ? a.check_every : 1;
+  const bool checking = a.x_ref != nullptr && a.tol > 0.0;
+  const bool final_err = a.x_ref != nullptr;
+  const int err_slot = MJ + MI;
+  const size_t V2 = (size_t)E * 2;
+  const int e_own = w < E ? w : -1;  // the entry this workgroup owns (E <= G)
+  const bool v_owner = e_own >= 0 && e_own < MJ, u_owner = e_own >= MJ && e_own < MJ + MI;
+
+  for (int q = tid; q < nr; q += T) {
+    zh[q] = a.z_in ? a.z_in[r0 + q] : a.b[r0 + q];
+    bl[q] = a.b[r0 + q];
+  }
+  for (int q = tid; q < nc; q += T) {
+    xh[q] = a.x_in ? a.x_in[cA + q] : 0.0;
+    xr[q] = a.x_ref ? a.x_ref[cA + q] : 0.0;
+  }
+  for (int q = tid; q < 7 * E + 2; q += T) bv[q] = 0.0;
+
+  auto slot = [&](int64_t q) -> int { return (int)((q - 1) & (kRing - 1)); };
+  auto refill = [&](int64_t first, int t0) {  // draws first .. first + 63 (lanes of the wave at t0)
+    const int l = tid - t0;
+    if (l >= 0 && l < 64) {
+      const int64_t q = first + l;
+      if (q <= K) {
+        int jj, ii;
+        draw_pair(a, a.k0 + q, jj, ii);
+        const int sl = (int)((q - 1) & (kRing - 1));
+        s_j[sl] = jj;
+        s_i[sl] = ii;
+        s_c0[sl] = a.col_off[jj];
+        s_nJ[sl] = (int)(a.col_off[jj + 1] - a.col_off[jj]);
+        s_r0[sl] = a.row_off[ii];
+        s_nI[sl] = (int)(a.row_off[ii + 1] - a.row_off[ii]);
+        s_cc[sl] = a.coef_col[jj];
+        s_cr[sl] = a.coef_row[ii];
+      }
+    }
+  };
+  // sizes and coefficients of iteration t (0 outside 1..K)
+  auto nJ_of = [&](int64_t t) -> int { return (t >= 1 && t <= K) ? s_nJ[slot(t)] : 0; };
+  auto nI_of = [&](int64_t t) -> int { return (t >= 1 && t <= K) ? s_nI[slot(t)] : 0; };
+  auto cc_of = [&](int64_t t) -> double { return (t >= 1 && t <= K) ? s_cc[slot(t)] : 0.0; };
+  auto cr_of = [&](int64_t t) -> double { return (t >= 1 && t <= K) ? s_cr[slot(t)] : 0.0; };
+  auto colslab = [&](int64_t t) -> TP* { return slabC + (size_t)(t % kPipeSlabs) * L.slabC; };
+  auto rowslab = [&](int64_t t) -> TP* { return slabR + (size_t)(t % kPipeSlabs) * L.slabR; };
+  // round t carries the error of x^{t-3} when a check is due (and the last error, of x^K)
+  auto err_round = [&](int64_t t) -> bool {
+    const int64_t k = t - 3;
+    return k >= 1 && k <= K && ((checking && k % ce == 0) || (final_err && k == K));
+  };
+  // entries of round t (polled in the broadcast and gathered by owners)
+  auto need = [&](int64_t t, int e) -> bool {  // (false for e < 0: a workgroup that owns no entry)
+    return (e >= 0 && e < MJ && e < nJ_of(t + 1)) || (e >= MJ && e < MJ + MI && e - MJ < nI_of(t)) ||
+           (e == err_slot && err_round(t));
+  };
+
+  // ---- copies into LDS
+  // Column slab of J_t: nJ runs of the owned rows, each c16 16-byte chunks (the column panels are
+  // padded to 16 entries, so a rounded-up run stays inside its column); run c at c * nrs.
+  auto colsrc = [&](int64_t t) -> const char* { return (const char*)(Acol + a.ldc * s_c0[slot(t)] + r0); };
+  auto col_direct = [&](int64_t t, int from, int l0, int nl) {  // chunks from `from` on
+    const int nJ = nr > 0 ? nJ_of(t) : 0;
+    if (nJ == 0) return;
+    const char* src = colsrc(t);
+    u32x4* dst = (u32x4*)colslab(t);
+    for (int d = from + l0; d < nJ * c16; d += nl) {
+      const int c = d / c16, p = d - c * c16;
+      dst[c * c16 + p] = *(gdword4*)(src + (int64_t)c * a.ldc * esz + 16 * p);
+    }
+  };
+  // Row slab of I_t: one run of nc x nI entries, copied in dwords when it starts on a dword (2-byte
+  // panels at an odd offset and a 2-byte tail go entry by entry).
+  auto rowsrc = [&](int64_t t) -> const TP* { return Arow + n * s_r0[slot(t)] + cA * nI_of(t); };
+  auto row_dwords = [&](int64_t t) -> int {
+    const int nI = nI_of(t);
+    if (nI == 0 || nc == 0 || ((uintptr_t)rowsrc(t) & 3) != 0) return 0;
+    return nc * nI * esz / 4;
+  };
+  auto row_direct = [&](int64_t t, int from_dw, int l0, int nl) {  // dwords from `from_dw` on, then entries
+    const int nI = nI_of(t);
+    if (nI == 0 || nc == 0) return;
+    const TP* src = rowsrc(t);
+    TP* dst = rowslab(t);
+    const int ndw = row_dwords(t);
+    for (int d = from_dw + l0; d < ndw; d += nl) ((uint32_t*)dst)[d] = ((gdword*)src)[d];
+    for (int e = ndw * 4 / esz + l0; e < nc * nI; e += nl) dst[e] = src[e];
+  };
+  // Raw rows of w_t (wr) and w'_t (wpr) for this workgroup's entry: up to two segments of doubles
+  // each (v owner: a row of H; u owner: a row of A, then a row of G at offset MJ).
+  struct Seg {
+    const double *s0, *s1, *s2, *s3;
+    double *d0, *d1, *d2, *d3;
+    int l0, l1, l2, l3;  // lengths (0: unused)
+  };
+  auto seg_add = [&](Seg& S, const double* src, double* dst, int len) {  // at most four per Seg
+    if (len <= 0) return;
+    if (S.l0 == 0) {
+      S.s0 = src, S.d0 = dst, S.l0 = len;
+    } else if (S.l1 == 0) {
+      S.s1 = src, S.d1 = dst, S.l1 = len;
+    } else if (S.l2 == 0) {
+      S.s2 = src, S.d2 = dst, S.l2 = len;
+    } else {
+      S.s3 = src, S.d3 = dst, S.l3 = len;
+    }
+  };
+  // flattened entry d of the segments: source and destination (d below the total)
+  auto seg_at = [&](const Seg& S, int d, const double*& src, double*& dst) {
+    if (d < S.l0) {
+      src = S.s0 + d, dst = S.d0 + d;
+    } else if ((d -= S.l0) < S.l1) {
+      src = S.s1 + d, dst = S.d1 + d;
+    } else if ((d -= S.l1) < S.l2) {
+      src = S.s2 + d, dst = S.d2 + d;
+    } else {
+      d -= S.l2;
+      src = S.s3 + d, dst = S.d3 + d;
+    }
+  };
+  auto segs_w = [&](Seg& S, int64_t t) {
+    if (!need(t, e_own)) return;
+    double* dst = wr + (size_t)(t & 1) * E;
+    if (v_owner) {
+      const int64_t C = s_c0[slot(t + 1)] + e_own;
+      if (nJ_of(t) > 0) seg_add(S, Hm + C * n + s_c0[slot(t)], dst, nJ_of(t));
+    } else if (u_owner) {
+      const int64_t R = s_r0[slot(t)] + (e_own - MJ);
+      if (nJ_of(t) > 0) seg_add(S, Arm + R * n + s_c0[slot(t)], dst, nJ_of(t));
+      if (nI_of(t - 1) > 0) seg_add(S, Gm + R * m + s_r0[slot(t - 1)], dst + MJ, nI_of(t - 1));
+    }
+  };
+  auto segs_wp = [&](Seg& S, int64_t t) {
+    if (!need(t, e_own)) return;
+    double* dst = wpr + (size_t)(t & 1) * E;
+    if (v_owner) {
+      const int64_t C = s_c0[slot(t + 1)] + e_own;
+      if (nJ_of(t - 1) > 0) seg_add(S, Hm + C * n + s_c0[slot(t - 1)], dst, nJ_of(t - 1));
+    } else if (u_owner) {
+      const int64_t R = s_r0[slot(t)] + (e_own - MJ);
+      if (nJ_of(t - 1) > 0) seg_add(S, Arm + R * n + s_c0[slot(t - 1)], dst, nJ_of(t - 1));
+      if (nI_of(t - 2) > 0) seg_add(S, Gm + R * m + s_r0[slot(t - 2)], dst + MJ, nI_of(t - 2));
+    }
+  };
+  auto seg_direct = [&](const Seg& S, int from, int l0, int nl) {  // flattened entries from `from` on
+    const int tot = S.l0 + S.l1 + S.l2 + S.l3;
+    for (int d = from + l0; d < tot; d += nl) {
+      const double* src;
+      double* dst;
+      seg_at(S, d, src, dst);
+      *dst = *(gdouble*)src;
+    }
+  };
+  auto seg_clear = [&](Seg& S) {
+    S.s0 = S.s1 = S.s2 = S.s3 = nullptr;
+    S.d0 = S.d1 = S.d2 = S.d3 = nullptr;
+    S.l0 = S.l1 = S.l2 = S.l3 = 0;
+  };
+
+  unsigned spins = 0;
+  int ok = 1;
+  auto give_up = [&]() -> bool {
+    if ((++spins & 63u) == 0) {
+      if (__hip_atomic_load(gs.timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+      if (spins > kSpinLimit) {
+        __hip_atomic_store(gs.timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+      }
+    }
+    return false;
+  };
+  const int p2 = lane & 1;
+  const bool first = p2 == 0;
+  // Gather: the sum over workgroups of entry e of the partial vectors of round t (one wave).
+  auto gather = [&](int64_t t, int e) -> double {
+    const unsigned long long* Pp = gs.part + (size_t)(t & (kPipeParts - 1)) * G * V2 + (size_t)e * 2;
+    const unsigned ep = (unsigned)(t + 1);
+    double acc = 0.0;
+    spins = 0;
+    for (int q0 = 0; q0 < G; q0 += 256) {
+      unsigned long long wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      while (ok) {
+        bool mine = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = q0 + k * 32 + (lane >> 1);
+          wd[k] = ld_u64(Pp + (size_t)(q < G ? q : G - 1) * V2 + p2);
+          const unsigned tg = first ? (unsigned)(wd[k] >> 32) : (unsigned)wd[k];
+          mine = mine && (q >= G || tg == ep);
+        }
+        if (__all(mine)) break;
+        if (give_up()) ok = 0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int q = q0 + k * 32 + (lane >> 1);
+        const unsigned long long o = mirror_word(wd[k]);
+        if (first && q < G) acc += tag_value(wd[k], o);
+      }
+    }
+    return group_sum(acc, 64);
+  };
+  // LDS handshake between waves of the workgroup: the writer's LDS stores are done before the flag
+  auto set_flag = [&](int* f, int v) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (lane == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  auto wait_flag = [&](int* f, int v) {
+    unsigned sp = 0;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < v) {
+      if (++sp > (kSpinLimit << 2)) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  };
+
+  // ---- partial sums of round t from z (owned rows) and x (owned columns):
+  //   v entries A_{J_{t+1}}^T z over owned rows (one wave), u entries A_{I_t} x - b + z (one wave),
+  //   and ||x - x_ref||^2 when due (the u wave)
+  auto part_v = [&](int64_t t, const double* zc) {  // whole wave
+    unsigned long long* P = gs.part + ((size_t)(t & (kPipeParts - 1)) * G + w) * V2;
+    const unsigned ep = (unsigned)(t + 1);
+    const int nJn = nJ_of(t + 1);
+    if (nJn == 0) return;
+    const TP* Sl = colslab(t + 1);
+    const int tq = lanes_per_item(64, nJn), per = 64 / tq, sub = lane % tq;
+    for (int c0 = 0; c0 < nJn; c0 += per) {
+      const int c = c0 + lane / tq;
+      const TP* col = Sl + (size_t)(c < nJn ? c : nJn - 1) * nrs;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int p = sub;
+      for (; p + 3 * tq < nr; p += 4 * tq) {
+        a0 += widen(col[p]) * zc[p];
+        a1 += widen(col[p + tq]) * zc[p + tq];
+        a2 += widen(col[p + 2 * tq]) * zc[p + 2 * tq];
+        a3 += widen(col[p + 3 * tq]) * zc[p + 3 * tq];
+      }
+      for (; p < nr; p += tq) a0 += widen(col[p]) * zc[p];
+      const double acc = group_sum((a0 + a1) + (a2 + a3), tq);
+      if (c < nJn && sub == 0) st_tagged(P, c, acc, ep);
+    }
+  };
+  auto part_u = [&](int64_t t, const double* xc, const double* zc, int zready) {  // whole wave
+    unsigned long long* P = gs.part + ((size_t)(t & (kPipeParts - 1)) * G + w) * V2;
+    const unsigned ep = (unsigned)(t + 1);
+    const int nIt = nI_of(t);
+    if (nIt > 0) {
+      const TP* Sr = rowslab(t);
+      const int64_t rI = s_r0[slot(t)];
+      bool waited = false;
+      for (int l0 = 0; l0 < nIt; l0 += 64) {
+        const int l = l0 + lane;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (l < nIt) {
+          int cc = 0;
+          for (; cc + 3 < nc; cc += 4) {
+            a0 += widen(Sr[cc * nIt + l]) * xc[cc];
+            a1 += widen(Sr[(cc + 1) * nIt + l]) * xc[cc + 1];
+            a2 += widen(Sr[(cc + 2) * nIt + l]) * xc[cc + 2];
+            a3 += widen(Sr[(cc + 3) * nIt + l]) * xc[cc + 3];
+          }
+          for (; cc < nc; ++cc) a0 += widen(Sr[cc * nIt + l]) * xc[cc];
+        }
+        double acc = (a0 + a1) + (a2 + a3);
+        // owned rows of I_t add z - b (z from the other wave: wait for it once)
+        const int64_t lo = rI + l0, hi = rI + (l0 + 64 < nIt ? l0 + 64 : nIt);
+        if (lo < r1 && hi > r0) {
+          if (!waited) {
+            wait_flag(&s_zflag, zready);
+            waited = true;
+          }
+          const int64_t gl = rI + l;
+          if (l < nIt && gl >= r0 && gl < r1) acc += zc[gl - r0] - bl[gl - r0];
+        }
+        if (l < nIt) st_tagged(P, MJ + l, acc, ep);
+      }
+    }
+    if (err_round(t)) {
+      double e = 0.0;
+      for (int cc = lane; cc < nc; cc += 64) {
+        const double d = xc[cc] - xr[cc];
+        e += d * d;
+      }
+      int width = 1;
+      while (width < nc && width < 64) width *= 2;
+      e = group_sum(e, width);
+      if (lane == 0) st_tagged(P, err_slot, e, ep);
+    }
+  };
+  // z^t = z^{t-1} - c'_t A_{J_t} v^t on owned rows (one wave), v^t = B^{t-1}[0, nJ)
+  auto zstep = [&](int64_t t, const double* vB) {
+    const int nJ = nJ_of(t);
+    const TP* Sl = colslab(t);
+    const double coef = cc_of(t);
+    const double* zo = zh + (size_t)((t - 1) & 3) * L.NR;
+    double* zn = zh + (size_t)(t & 3) * L.NR;
+    for (int p = lane; p < nr; p += 64) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int c = 0;
+      for (; c + 3 < nJ; c += 4) {
+        a0 += widen(Sl[c * nrs + p]) * vB[c];
+        a1 += widen(Sl[(c + 1) * nrs + p]) * vB[c + 1];
+        a2 += widen(Sl[(c + 2) * nrs + p]) * vB[c + 2];
+        a3 += widen(Sl[(c + 3) * nrs + p]) * vB[c + 3];
+      }
+      for (; c < nJ; ++c) a0 += widen(Sl[c * nrs + p]) * vB[c];
+      zn[p] = zo[p] - coef * ((a0 + a1) + (a2 + a3));
+    }
+  };
+  // x^t = x^{t-1} - c_t A_{I_t}^T u^t on owned columns (one wave), u^t = B^t[MJ, MJ + nI)
+  auto xstep = [&](int64_t t, const double* uB) {
+    const int nI = nI_of(t);
+    const TP* Sl = rowslab(t);
+    const double coef = cr_of(t);
+    const double* xo = xh + (size_t)((t - 1) & 3) * L.NC;
+    double* xn = xh + (size_t)(t & 3) * L.NC;
+    const int tpc = lanes_per_item(64, nc), cp = 64 / tpc, sub = lane % tpc;
+    for (int c0 = 0; c0 < nc; c0 += cp) {
+      const int cc = c0 + lane / tpc;
+      const TP* col = Sl + (size_t)(cc < nc ? cc : nc - 1) * nI;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int l = sub;
+      for (; l + 3 * tpc < nI; l += 4 * tpc) {
+        a0 += widen(col[l]) * uB[l];
+        a1 += widen(col[l + tpc]) * uB[l + tpc];
+        a2 += widen(col[l + 2 * tpc]) * uB[l + 2 * tpc];
+        a3 += widen(col[l + 3 * tpc]) * uB[l + 3 * tpc];
+      }
+      for (; l < nI; l += tpc) a0 += widen(col[l]) * uB[l];
+      const double acc = group_sum((a0 + a1) + (a2 + a3), tpc);
+      if (cc < nc && sub == 0) xn[cc] = xo[cc] - coef * acc;
+    }
+  };
+
+  // ---- wave 0: the broadcast (8 entries per lane pair: entry q = 32 k + lane / 2, first lanes)
+  double W1[8], W2[8];  // w_{r+1} and w'_{r+2} of this workgroup's entry, scaled, in that layout
+  double pc = 0.0;      // -w'_{r+1} . B^{r-1} of this workgroup's entry
+  // scaled coefficient vector of round t from raw rows (both apply to B^{t-1} / B^{t-2} with the
+  // coefficients of iterations tv (v part) and tu (u part))
+  auto load_w = [&](double* Wv, const double* raw, bool has, int64_t tv, int64_t tu) {
+    const int nv = has && (v_owner || u_owner) ? nJ_of(tv) : 0;
+    const int nu = has && u_owner ? nI_of(tu) : 0;
+    const double cv = cc_of(tv), cu = cr_of(tu);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int q = k * 32 + (lane >> 1);
+      double v = 0.0;
+      if (first && q < nv) v = cv * raw[q];
+      else if (first && q >= MJ && q - MJ < nu) v = cu * raw[q];
+      Wv[k] = v;
+    }
+  };
+
+  // ---------------- prologue
+  for (int64_t f = 1; f <= 128 && f <= K; f += 64) refill(f, 64 * (int)((f / 64) & 3));
+  int64_t filled_to = 128;
+  if (tid == 0) {
+    s_ok = 1;
+    s_zflag = 0;
+    s_gflag = -1;
+  }
+  lds_barrier();
+  {
+    // slabs of J_1..J_4 and I_1..I_3; raw rows of w_1, w_2, w'_2, w'_3 (direct copies)
+    for (int64_t t = 1; t <= 4; ++t) col_direct(t, 0, tid, T);
+    for (int64_t t = 1; t <= 3; ++t) row_direct(t, 0, tid, T);
+    Seg S;  // at most two segments per vector
+    for (int v = 0; v < 4; ++v) {
+      seg_clear(S);
+      if (v < 2) segs_w(S, 1 + v);
+      else segs_wp(S, v);
+      seg_direct(S, 0, tid, T);
+    }
+  }
+  lds_barrier();
+  // partial sums of rounds 0, 1, 2 from x^0, z^0; the owner gathers rounds 0 and 1
+  if (tid >= 64 && tid < 128) {
+    part_v(0, zh);
+    part_v(1, zh);
+    part_v(2, zh);
+  } else if (tid >= 128 && tid < 192) {
+    part_u(1, xh, zh, 0);
+    part_u(2, xh, zh, 0);
+  } else if (tid >= 192) {
+    const double g0 = need(0, e_own) ? gather(0, e_own) : 0.0;
+    const double g1 = need(1, e_own) ? gather(1, e_own) : 0.0;
+    if (lane == 0) {
+      gat[0] = g0;
+      gat[1] = g1;
+    }
+    set_flag(&s_gflag, 1);
+  }
+  if (!ok) s_ok = 0;
+  lds_barrier();
+  if (tid < 64) {
+    load_w(W1, wr + (size_t)(1 & 1) * E, need(1, e_own), 1, 0);    // w_1 . B^0
+    load_w(W2, wpr + (size_t)(2 & 1) * E, need(2, e_own), 1, 0);   // w'_2 . B^0
+    if (e_own >= 0 && need(0, e_own) && lane < kCopies) {
+      unsigned long long* S0 = gs.gsum + (size_t)(1 % kGridSumRing) * kCopies * V2;
+      st_tagged(S0 + (size_t)lane * V2, e_own, gat[0], 1u);
+    }
+  }
+
+  int status = 0, stopped = 0;
+  int64_t last_k = a.k0;
+  double last_err2 = -1.0;
+  int64_t last_check = -1;
+  bool alive = s_ok != 0;
+  int64_t r = 0;
+  for (; alive; ++r) {
+    if (tid < 64) {
+      // ---- wave 0: poll B^r, publish this workgroup's entry of B^{r+1}, hand B^r over
+      const unsigned epB = (unsigned)(r + 1);
+      const unsigned long long* Sg =
+          gs.gsum + (size_t)(epB % kGridSumRing) * kCopies * V2 + (size_t)(w % kCopies) * V2;
+      unsigned needm = 0;  // entries of B^r this lane reads, one bit per register
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int q = k * 32 + (lane >> 1);
+        if (q < E && need(r, q)) needm |= 1u << k;
+      }
+      const bool any = __any(needm != 0);
+      unsigned long long wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      spins = 0;
+      while (any && ok) {
+        bool mine = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = k * 32 + (lane >> 1);
+          wd[k] = ld_u64(Sg + (size_t)2 * (q < E ? q : E - 1) + p2);
+          const unsigned tg = first ? (unsigned)(wd[k] >> 32) : (unsigned)wd[k];
+          mine = mine && (((needm >> k) & 1u) == 0 || tg == epB);
+        }
+        if (__all(mine)) break;
+        if (give_up()) ok = 0;
+      }
+      double vals[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int q = k * 32 + (lane >> 1);
+        const unsigned long long o = mirror_word(wd[k]);
+        vals[k] = (first && ((needm >> k) & 1u)) ? tag_value(wd[k], o) : 0.0;
+      }
+      if (e_own >= 0 && need(r + 1, e_own)) {
+        wait_flag(&s_gflag, (int)(r + 1));
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d += W1[k] * vals[k];
+        d = group_sum(d, 64);
+        const double val = gat[(r + 1) & 1] + pc - d;
+        if (lane < kCopies) {
+          unsigned long long* Sn = gs.gsum + (size_t)((r + 2) % kGridSumRing) * kCopies * V2;
+          st_tagged(Sn + (size_t)lane * V2, e_own, val, (unsigned)(r + 2));
+        }
+      }
+      double d2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) d2 += W2[k] * vals[k];
+      pc = -group_sum(d2, 64);
+      double* Bn = bv + (size_t)(r % 3) * E;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int q = k * 32 + (lane >> 1);
+        if (first && q < E) Bn[q] = vals[k];
+      }
+    }
+    if (!ok) s_ok = 0;
+    lds_barrier();  // B^r in LDS; the helpers' work of round r - 1 is done
+    if (s_ok == 0) {
+      alive = false;
+      break;
+    }
+    if (tid == 0 && w == 0 && a.trace_j && r >= 1 && r <= K) {
+      a.trace_j[r - 1] = s_j[slot(r)];
+      a.trace_i[r - 1] = s_i[slot(r)];
+    }
+    const double* Bc = bv + (size_t)(r % 3) * E;
+    if (err_round(r)) {  // the error of x^{r-3}
+      const double e2 = Bc[err_slot];
+      const int64_t k = r - 3;
+      last_err2 = e2;
+      last_check = a.k0 + k;
+      const double rel = sqrt(e2) / sqrt(a.xref_sq);
+      const bool stop = checking && (rel < a.tol || !isfinite(e2) || rel > 1e6);
+      if (stop || k == K) {
+        stopped = stop ? 1 : 0;
+        status = !checking ? 0 : (rel < a.tol ? 0 : ((!isfinite(e2) || rel > 1e6) ? 2 : 1));
+        last_k = a.k0 + k;
+        const double* zk = zh + (size_t)(k & 3) * L.NR;
+        const double* xk = xh + (size_t)(k & 3) * L.NC;
+        for (int p = tid; p < nr; p += T)
+          if (a.z_out) a.z_out[r0 + p] = zk[p];
+        for (int p = tid; p < nc; p += T) a.x_out[cA + p] = xk[p];
+        break;
+      }
+    }
+    if (!final_err && r == K) {  // the last step: x^K (z^K was formed one round earlier)
+      if (tid >= 128 && tid < 192 && nc > 0) xstep(K, Bc + MJ);
+      lds_barrier();
+      last_k = a.k0 + K;
+      break;
+    }
+    if (tid < 64) {
+      // w_{r+2} and w'_{r+3}, both applied to B^{r+1}
+      load_w(W1, wr + (size_t)((r + 2) & 1) * E, need(r + 2, e_own), r + 2, r + 1);
+      load_w(W2, wpr + (size_t)((r + 3) & 1) * E, need(r + 3, e_own), r + 2, r + 1);
+      continue;
+    }
+    // ---- waves 1..3: round r of the helpers
+    if (tid >= 192 && filled_to < K && r + 40 > filled_to) refill(filled_to + 1, 192);
+    if (filled_to < K && r + 40 > filled_to) filled_to += 64;
+    // copies for later rounds, issued now and written to LDS at the end of the round: wave 1 the
+    // column slab of J_{r+5} (16-byte chunks), wave 2 the row slab of I_{r+4} (dwords), wave 3 the
+    // raw rows of w_{r+3} and w'_{r+4} (doubles)
+    uint32_t stg[kPipeStage];
+    int stl[kPipeStage / 2];
+    const int hw = (tid >> 6) - 1;
+    int ncol = 0, nrow = 0;
+    Seg S;
+    seg_clear(S);
+#pragma unroll
+    for (int k = 0; k < kPipeStage / 2; ++k) stl[k] = -1;
+    if (hw == 0) {
+      const int64_t t = r + 5;
+      ncol = nr > 0 ? nJ_of(t) * c16 : 0;
+      if (ncol > 0) {
+        const char* src = colsrc(t);
+        const int64_t cstride = a.ldc * esz;
+        const int dbase = (int)((const uint32_t*)colslab(t) - (const uint32_t*)lds);
+        int c = lane / c16, p = lane - c * c16;
+        const int sc = 64 / c16, sp = 64 - sc * c16;
+#pragma unroll
+        for (int k = 0; k < kPipeStage / 4; ++k) {
+          const int d = lane + 64 * k;
+          if (d < ncol) {
+            const u32x4 v = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
+            stg[4 * k] = v.x;
+            stg[4 * k + 1] = v.y;
+            stg[4 * k + 2] = v.z;
+            stg[4 * k + 3] = v.w;
+            stl[k] = dbase + 4 * (c * c16 + p);
+          }
+          p += sp;
+          c += sc;
+          if (p >= c16) {
+            p -= c16;
+            ++c;
+          }
+        }
+      }
+    } else if (hw == 1) {
+      nrow = row_dwords(r + 4);
+      if (nrow > 0) {
+        gdword* src = (gdword*)rowsrc(r + 4);
+#pragma unroll
+        for (int k = 0; k < kPipeStage; ++k) {
+          const int d = lane + 64 * k;
+          if (d < nrow) stg[k] = src[d];
+        }
+      }
+    } else {
+      segs_w(S, r + 3);
+      segs_wp(S, r + 4);
+      const int tot = S.l0 + S.l1 + S.l2 + S.l3;
+#pragma unroll
+      for (int k = 0; k < kPipeStage / 2; ++k) {
+        const int d = lane + 64 * k;
+        if (d < tot) {
+          const double* src;
+          double* dst;
+          seg_at(S, d, src, dst);
+          const double v = *(gdouble*)src;
+          stg[2 * k] = (uint32_t)__double2loint(v);
+          stg[2 * k + 1] = (uint32_t)__double2hiint(v);
+          stl[k] = (int)(dst - lds);
+        }
+      }
+    }
+    const int64_t tz = r + 1 <= K ? r + 1 : K, tx = r <= K ? r : K;
+    const double* zc = zh + (size_t)(tz & 3) * L.NR;
+    const double* xc = xh + (size_t)(tx & 3) * L.NC;
+    if (tid < 128) {
+      // wave 1: z^{r+1}, then the v entries of round r + 3 from it
+      if (r + 1 <= K && nr > 0) zstep(r + 1, Bc);
+      set_flag(&s_zflag, (int)(r + 1));
+      part_v(r + 3, zc);
+    } else if (tid < 192) {
+      // wave 2: x^r, then the u entries (and the error) of round r + 3
+      if (r >= 1 && r <= K && nc > 0) xstep(r, Bc + MJ);
+      part_u(r + 3, xc, zc, (int)(r + 1));
+    } else {
+      // wave 3: the owner's sum of round r + 2
+      if (need(r + 2, e_own)) {
+        const double g = gather(r + 2, e_own);
+        if (lane == 0) gat[(r + 2) & 1] = g;
+      }
+      set_flag(&s_gflag, (int)(r + 2));
+    }
+    // the staged copies land in LDS; what did not fit is copied directly
+    if (hw == 0) {
+      uint32_t* const ldw = (uint32_t*)lds;
+#pragma unroll
+      for (int k = 0; k < kPipeStage / 4; ++k)
+        if (stl[k] >= 0) *(u32x4*)(ldw + stl[k]) = u32x4{stg[4 * k], stg[4 * k + 1], stg[4 * k + 2], stg[4 * k + 3]};
+      if (ncol > 64 * (kPipeStage / 4)) col_direct(r + 5, 64 * (kPipeStage / 4), lane, 64);
+    } else if (hw == 1) {
+      uint32_t* const dst = (uint32_t*)rowslab(r + 4);
+#pragma unroll
+      for (int k = 0; k < kPipeStage; ++k) {
+        const int d = lane + 64 * k;
+        if (d < nrow) dst[d] = stg[k];
+      }
+      row_direct(r + 4, 64 * kPipeStage, lane, 64);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kPipeStage / 2; ++k)
+        if (stl[k] >= 0) lds[stl[k]] = __hiloint2double((int)stg[2 * k + 1], (int)stg[2 * k]);
+      seg_direct(S, 64 * (kPipeStage / 2), lane, 64);
+    }
+  }
+  wait_mem();
+  if (alive && !final_err) {  // x^K, z^K
+    const double* zk = zh + (size_t)(K & 3) * L.NR;
+    const double* xk = xh + (size_t)(K & 3) * L.NC;
+    for (int p = tid; p < nr; p += T)
+      if (a.z_out) a.z_out[r0 + p] = zk[p];
+    for (int p = tid; p < nc; p += T) a.x_out[cA + p] = xk[p];
+  }
+  if (w == 0 && tid == 0) {
+    a.status->status = alive ? status : -4;
+    a.status->stopped = stopped;
+    a.status->last_k = last_k;
+    a.status->err2 = last_err2;
+    a.status->check_k = last_check;
+  }
+}
+
+// A as a row-major FP64 matrix (row r at out + r n) from the row panels (block i: n x |I_i|
+// column-major at n row_off[i]); one workgroup per row block, reads along the panel.
+template <typename TP>
+__global__ void __launch_bounds__(256) unpack_rows_kernel(const TP* __restrict__ Arow, int64_t n,
+                                                          const int64_t* __restrict__ row_off, int32_t s,
+                                                          double* __restrict__ out) {
+  for (int64_t i = blockIdx.x; i < s; i += gridDim.x) {
+    const int64_t r0 = row_off[i];
+    const int64_t nI = row_off[i + 1] - r0;
+    const TP* P = Arow + n * r0;
+    for (int64_t e = threadIdx.x; e < nI * n; e += blockDim.x) {
+      const int64_t c = e / nI, l = e - c * nI;
+      out[(r0 + l) * n + c] = widen(P[e]);
+    }
+  }
+}
+
 }  // namespace
 
 size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype, bool row_lds) {
@@ -747,6 +1492,54 @@ hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_d
     SolveArgs aa = a;
     GridSync gg = gs;
     void* args[] = {&aa, &gg};
+    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kGridThreads), args, (unsigned)lds, st);
+  });
+}
+
+}  // namespace rebk
+
+namespace rebk {
+
+size_t pipe_solve_lds_bytes(const SolveArgs& a, int grid, int stride, int panel_dtype) {
+  const size_t esz = panel_dtype == 0 ? 8 : (panel_dtype == 1 ? 4 : 2);
+  const PipeLayout L = pipe_layout(a.m, a.n, a.max_nI, a.max_nJ, stride, grid, (int)esz);
+  return L.dbl * sizeof(double) + (size_t)kPipeSlabs * (L.slabC + L.slabR) * esz + 64;
+}
+
+hipError_t pipe_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    const void* k = (const void*)pipe_solve_kernel<TP>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kGridThreads, lds_bytes);
+  });
+}
+
+hipError_t launch_unpack_rows(const void* Arow, int panel_dtype, int64_t n, const int64_t* row_off_d, int32_t s,
+                              double* out, hipStream_t st) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    const unsigned g = (unsigned)(s < 65536 ? s : 65536);
+    hipLaunchKernelGGL(unpack_rows_kernel<TP>, dim3(g), dim3(256), 0, st, (const TP*)Arow, n, row_off_d, s, out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_pipe_solve(const SolveArgs& a, const GridSync& gs, const double* Gm, const double* Hm,
+                             const double* Arm, int panel_dtype, int grid, hipStream_t st) {
+  return dev::dispatch_panel(panel_dtype, [&](auto tag) -> hipError_t {
+    using TP = typename decltype(tag)::T;
+    const void* k = (const void*)pipe_solve_kernel<TP>;
+    const size_t lds = pipe_solve_lds_bytes(a, grid, gs.stride, panel_dtype);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    SolveArgs aa = a;
+    GridSync gg = gs;
+    const double* g = Gm;
+    const double* h = Hm;
+    const double* ar = Arm;
+    void* args[] = {&aa, &gg, (void*)&g, (void*)&h, (void*)&ar};
     return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kGridThreads), args, (unsigned)lds, st);
   });
 }

@@ -146,6 +146,17 @@ hipError_t launch_grid_solve(const SolveArgs& a, const GridSync& gs, int panel_d
                              hipStream_t st);
 size_t grid_solve_lds_bytes(const SolveArgs& a, int grid, int panel_dtype, bool row_lds);
 hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, bool row_lds, int* blocks_per_cu);
+// Pipelined whole-chip kernel (rebk_grid.hip): G = A A^T (m x m), H = A^T A (n x n) and A
+// row-major (m x n), all FP64 from the stored panel values; GridSync.part holds 4 x grid vectors.
+// Its broadcast vector has at most kPipeMaxStride entries (8 registers per lane of one wave).
+constexpr int kPipeMaxStride = 256;
+hipError_t launch_pipe_solve(const SolveArgs& a, const GridSync& gs, const double* Gm, const double* Hm,
+                             const double* Arm, int panel_dtype, int grid, hipStream_t st);
+size_t pipe_solve_lds_bytes(const SolveArgs& a, int grid, int stride, int panel_dtype);
+hipError_t pipe_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_per_cu);
+// A (stored panel values) as a row-major FP64 m x n matrix
+hipError_t launch_unpack_rows(const void* Arow, int panel_dtype, int64_t n, const int64_t* row_off_d, int32_t s,
+                              double* out, hipStream_t st);
 hipError_t launch_residual(const void* Arow, const void* Acol, int panel_dtype, const SolveArgs& a,
                            const double* x, const double* z, double* partials, int nparts, hipStream_t st);
 size_t batch_lds_bytes(int64_t m, int64_t n, int R, int max_nJ, int max_nI, int threads);

@@ -58,6 +58,9 @@ def test_host_validation_without_device():
     assert lib.rebk_solve_ex(None, None, None) == N.ERR_INVALID
     assert lib.rebk_solve_ex_static(None, None, None) == N.ERR_INVALID
     assert lib.rebk_get_weights(None, None, None) == N.ERR_INVALID
+    ms = ctypes.c_double(-1.0)
+    assert lib.rebk_pipe_prepare(None, ctypes.byref(ms)) == N.ERR_INVALID and ms.value == 0.0
+    lib.rebk_pipe_release(None)
     lib.rebk_destroy(None)
 
 

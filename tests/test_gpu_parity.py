@@ -13,7 +13,7 @@ from tests._helpers import RTOL_F64, gpu_vs_oracle, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["workgroup", "grid"]
+KERNELS = ["workgroup", "grid", "pipe"]
 
 
 @pytest.fixture(scope="module")
@@ -288,21 +288,24 @@ def cfg2():
     return W.rank1500_20000x2000()
 
 
-def test_rank1500_20000x2000_prefix(rebk, oracle_lib, cfg2):
-    """Full size, the launch configuration of the benchmark: 300 iterations against the oracle."""
-    print("case 20000x2000 prefix", flush=True)
-    gpu_vs_oracle(rebk, oracle_lib, cfg2, kernel="grid", max_iter=300)
+@pytest.mark.parametrize("kernel,panel", [("grid", "f64"), ("grid", "f32"), ("pipe", "f32")])
+def test_rank1500_20000x2000_prefix(rebk, oracle_lib, cfg2, kernel, panel):
+    """Full size, the launch configurations of the benchmark: 300 iterations against the oracle."""
+    S = cfg2
+    print(f"case 20000x2000 prefix kernel={kernel} panels={panel}", flush=True)
+    A_stored = S.A if panel == "f64" else W.round_to_f32(S.A)
+    gpu_vs_oracle(rebk, oracle_lib, S, kernel=kernel, max_iter=300, panel=panel, A_stored=A_stored)
 
 
-@pytest.mark.parametrize("panel", ["f64", "f32"])
-def test_rank1500_20000x2000_converges(rebk, oracle_lib, cfg2, panel):
+@pytest.mark.parametrize("kernel,panel", [("grid", "f64"), ("grid", "f32"), ("pipe", "f32")])
+def test_rank1500_20000x2000_converges(rebk, oracle_lib, cfg2, kernel, panel):
     """Full run to relative error 1e-6 against A^+ b; the whole block sequence is the oracle's."""
     S = cfg2
-    print(f"case 20000x2000 full solve panels={panel}", flush=True)
+    print(f"case 20000x2000 full solve kernel={kernel} panels={panel}", flush=True)
     A_stored = S.A if panel == "f64" else W.round_to_f32(S.A)
     solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
     out = solver.solve_ex(to_dev(S.b), max_iter=400000, x_ref=to_dev(S.x_ref), tol=1e-6, check_every=1,
-                          trace=True, kernel="grid")
+                          trace=True, kernel=kernel)
     r = out["result"]
     assert r.status == "ok", r
     assert rel(out["x"].cpu().numpy(), S.x_ref) < 1e-6
