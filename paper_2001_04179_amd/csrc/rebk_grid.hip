@@ -765,6 +765,33 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 using gdword4 = const __attribute__((address_space(1))) u32x4;
 using gdouble = const __attribute__((address_space(1))) double;
 
+// sum over i < cnt of a[i sa] b[i sb] in FP64, eight loads of each operand issued before the
+// products of a step (one wave per SIMD: nothing else hides the LDS latency)
+template <typename TP>
+__device__ __forceinline__ double dot_strided(const TP* a, int sa, const double* b, int sb, int cnt) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 7 < cnt; i += 8) {
+    TP av[8];
+    double bv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      av[k] = a[(i + k) * sa];
+      bv[k] = b[(i + k) * sb];
+    }
+    s0 += widen(av[0]) * bv[0];
+    s1 += widen(av[1]) * bv[1];
+    s2 += widen(av[2]) * bv[2];
+    s3 += widen(av[3]) * bv[3];
+    s0 += widen(av[4]) * bv[4];
+    s1 += widen(av[5]) * bv[5];
+    s2 += widen(av[6]) * bv[6];
+    s3 += widen(av[7]) * bv[7];
+  }
+  for (; i < cnt; ++i) s0 += widen(a[i * sa]) * b[i * sb];
+  return (s0 + s1) + (s2 + s3);
+}
+
 template <typename TP>
 __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, GridSync gs,
                                                                   const double* __restrict__ Gm,
@@ -984,11 +1011,17 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     for (int q0 = 0; q0 < G; q0 += 256) {
       unsigned long long wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       while (ok) {
-        bool mine = true;
+        // all eight loads in flight before any is inspected (a use between them would make each
+        // wait for the previous one)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int q = q0 + k * 32 + (lane >> 1);
           wd[k] = ld_u64(Pp + (size_t)(q < G ? q : G - 1) * V2 + p2);
+        }
+        bool mine = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = q0 + k * 32 + (lane >> 1);
           const unsigned tg = first ? (unsigned)(wd[k] >> 32) : (unsigned)wd[k];
           mine = mine && (q >= G || tg == ep);
         }
@@ -1033,16 +1066,8 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     for (int c0 = 0; c0 < nJn; c0 += per) {
       const int c = c0 + lane / tq;
       const TP* col = Sl + (size_t)(c < nJn ? c : nJn - 1) * nrs;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int p = sub;
-      for (; p + 3 * tq < nr; p += 4 * tq) {
-        a0 += widen(col[p]) * zc[p];
-        a1 += widen(col[p + tq]) * zc[p + tq];
-        a2 += widen(col[p + 2 * tq]) * zc[p + 2 * tq];
-        a3 += widen(col[p + 3 * tq]) * zc[p + 3 * tq];
-      }
-      for (; p < nr; p += tq) a0 += widen(col[p]) * zc[p];
-      const double acc = group_sum((a0 + a1) + (a2 + a3), tq);
+      const int cnt = sub < nr ? (nr - sub + tq - 1) / tq : 0;
+      const double acc = group_sum(dot_strided(col + sub, tq, zc + sub, tq, cnt), tq);
       if (c < nJn && sub == 0) st_tagged(P, c, acc, ep);
     }
   };
@@ -1056,18 +1081,7 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
       bool waited = false;
       for (int l0 = 0; l0 < nIt; l0 += 64) {
         const int l = l0 + lane;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        if (l < nIt) {
-          int cc = 0;
-          for (; cc + 3 < nc; cc += 4) {
-            a0 += widen(Sr[cc * nIt + l]) * xc[cc];
-            a1 += widen(Sr[(cc + 1) * nIt + l]) * xc[cc + 1];
-            a2 += widen(Sr[(cc + 2) * nIt + l]) * xc[cc + 2];
-            a3 += widen(Sr[(cc + 3) * nIt + l]) * xc[cc + 3];
-          }
-          for (; cc < nc; ++cc) a0 += widen(Sr[cc * nIt + l]) * xc[cc];
-        }
-        double acc = (a0 + a1) + (a2 + a3);
+        double acc = l < nIt ? dot_strided(Sr + l, nIt, xc, 1, nc) : 0.0;
         // owned rows of I_t add z - b (z from the other wave: wait for it once)
         const int64_t lo = rI + l0, hi = rI + (l0 + 64 < nIt ? l0 + 64 : nIt);
         if (lo < r1 && hi > r0) {
@@ -1100,18 +1114,7 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     const double coef = cc_of(t);
     const double* zo = zh + (size_t)((t - 1) & 3) * L.NR;
     double* zn = zh + (size_t)(t & 3) * L.NR;
-    for (int p = lane; p < nr; p += 64) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int c = 0;
-      for (; c + 3 < nJ; c += 4) {
-        a0 += widen(Sl[c * nrs + p]) * vB[c];
-        a1 += widen(Sl[(c + 1) * nrs + p]) * vB[c + 1];
-        a2 += widen(Sl[(c + 2) * nrs + p]) * vB[c + 2];
-        a3 += widen(Sl[(c + 3) * nrs + p]) * vB[c + 3];
-      }
-      for (; c < nJ; ++c) a0 += widen(Sl[c * nrs + p]) * vB[c];
-      zn[p] = zo[p] - coef * ((a0 + a1) + (a2 + a3));
-    }
+    for (int p = lane; p < nr; p += 64) zn[p] = zo[p] - coef * dot_strided(Sl + p, nrs, vB, 1, nJ);
   };
   // x^t = x^{t-1} - c_t A_{I_t}^T u^t on owned columns (one wave), u^t = B^t[MJ, MJ + nI)
   auto xstep = [&](int64_t t, const double* uB) {
@@ -1124,36 +1127,128 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     for (int c0 = 0; c0 < nc; c0 += cp) {
       const int cc = c0 + lane / tpc;
       const TP* col = Sl + (size_t)(cc < nc ? cc : nc - 1) * nI;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int l = sub;
-      for (; l + 3 * tpc < nI; l += 4 * tpc) {
-        a0 += widen(col[l]) * uB[l];
-        a1 += widen(col[l + tpc]) * uB[l + tpc];
-        a2 += widen(col[l + 2 * tpc]) * uB[l + 2 * tpc];
-        a3 += widen(col[l + 3 * tpc]) * uB[l + 3 * tpc];
-      }
-      for (; l < nI; l += tpc) a0 += widen(col[l]) * uB[l];
-      const double acc = group_sum((a0 + a1) + (a2 + a3), tpc);
+      const int cnt = sub < nI ? (nI - sub + tpc - 1) / tpc : 0;
+      const double acc = group_sum(dot_strided(col + sub, tpc, uB + sub, tpc, cnt), tpc);
       if (cc < nc && sub == 0) xn[cc] = xo[cc] - coef * acc;
     }
   };
 
   // ---- wave 0: the broadcast (8 entries per lane pair: entry q = 32 k + lane / 2, first lanes)
-  double W1[8], W2[8];  // w_{r+1} and w'_{r+2} of this workgroup's entry, scaled, in that layout
-  double pc = 0.0;      // -w'_{r+1} . B^{r-1} of this workgroup's entry
-  // scaled coefficient vector of round t from raw rows (both apply to B^{t-1} / B^{t-2} with the
-  // coefficients of iterations tv (v part) and tu (u part))
-  auto load_w = [&](double* Wv, const double* raw, bool has, int64_t tv, int64_t tu) {
+  double pc = 0.0;  // -w'_{r+1} . B^{r-1} of this workgroup's entry
+  // (scaled raw rows) . vals over the wave: the v part scaled by c'_{tv} over nJ(tv) entries, the u
+  // part by c_{tu} over nI(tu) entries (u owners only); vals hold a broadcast vector in the
+  // 32 k + lane / 2 layout (first lanes)
+  auto dot_raw = [&](const double* raw, bool has, int64_t tv, int64_t tu, const double* vals) -> double {
     const int nv = has && (v_owner || u_owner) ? nJ_of(tv) : 0;
     const int nu = has && u_owner ? nI_of(tu) : 0;
     const double cv = cc_of(tv), cu = cr_of(tu);
+    double d = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int q = k * 32 + (lane >> 1);
-      double v = 0.0;
-      if (first && q < nv) v = cv * raw[q];
-      else if (first && q >= MJ && q - MJ < nu) v = cu * raw[q];
-      Wv[k] = v;
+      const bool inv = first && q < nv, inu = first && q >= MJ && q - MJ < nu;
+      const double rw = (inv || inu) ? raw[q] : 0.0;
+      d += ((inv ? cv : cu) * rw) * vals[k];
+    }
+    return group_sum(d, 64);
+  };
+
+  // Copies in flight from one round to the next (helper waves; wave hw + 1): stage(r) issues the
+  // loads for round r + 1 (wave 1 the column slab of J_{r+5} in 16-byte chunks, wave 2 the row slab
+  // of I_{r+4} in dwords, wave 3 the raw rows of w_{r+4} and w'_{r+5} in doubles), left in flight
+  // across the wait for the broadcast; commit(r + 1) writes them to LDS and copies directly what
+  // did not fit.
+  const int hw = (tid >> 6) - 1;
+  uint32_t stg[kPipeStage];
+  int stl[kPipeStage / 2];
+  int ncol = 0, nrow = 0;
+  Seg S;
+  seg_clear(S);
+#pragma unroll
+  for (int k = 0; k < kPipeStage / 2; ++k) stl[k] = -1;
+  auto stage = [&](int64_t r) {
+#pragma unroll
+    for (int k = 0; k < kPipeStage / 2; ++k) stl[k] = -1;
+    ncol = 0;
+    nrow = 0;
+    seg_clear(S);
+    if (hw == 0) {
+      const int64_t t = r + 5;
+      ncol = nr > 0 ? nJ_of(t) * c16 : 0;
+      if (ncol > 0) {
+        const char* src = colsrc(t);
+        const int64_t cstride = a.ldc * esz;
+        const int dbase = (int)((const uint32_t*)colslab(t) - (const uint32_t*)lds);
+        int c = lane / c16, p = lane - c * c16;
+        const int sc = 64 / c16, sp = 64 - sc * c16;
+#pragma unroll
+        for (int k = 0; k < kPipeStage / 4; ++k) {
+          const int d = lane + 64 * k;
+          if (d < ncol) {
+            const u32x4 v = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
+            stg[4 * k] = v.x;
+            stg[4 * k + 1] = v.y;
+            stg[4 * k + 2] = v.z;
+            stg[4 * k + 3] = v.w;
+            stl[k] = dbase + 4 * (c * c16 + p);
+          }
+          p += sp;
+          c += sc;
+          if (p >= c16) {
+            p -= c16;
+            ++c;
+          }
+        }
+      }
+    } else if (hw == 1) {
+      nrow = row_dwords(r + 4);
+      if (nrow > 0) {
+        gdword* src = (gdword*)rowsrc(r + 4);
+#pragma unroll
+        for (int k = 0; k < kPipeStage; ++k) {
+          const int d = lane + 64 * k;
+          if (d < nrow) stg[k] = src[d];
+        }
+      }
+    } else {
+      segs_w(S, r + 4);
+      segs_wp(S, r + 5);
+      const int tot = S.l0 + S.l1 + S.l2 + S.l3;
+#pragma unroll
+      for (int k = 0; k < kPipeStage / 2; ++k) {
+        const int d = lane + 64 * k;
+        if (d < tot) {
+          const double* src;
+          double* dst;
+          seg_at(S, d, src, dst);
+          const double v = *(gdouble*)src;
+          stg[2 * k] = (uint32_t)__double2loint(v);
+          stg[2 * k + 1] = (uint32_t)__double2hiint(v);
+          stl[k] = (int)(dst - lds);
+        }
+      }
+    }
+  };
+  auto commit = [&](int64_t r) {
+    if (hw == 0) {
+      uint32_t* const ldw = (uint32_t*)lds;
+#pragma unroll
+      for (int k = 0; k < kPipeStage / 4; ++k)
+        if (stl[k] >= 0) *(u32x4*)(ldw + stl[k]) = u32x4{stg[4 * k], stg[4 * k + 1], stg[4 * k + 2], stg[4 * k + 3]};
+      if (ncol > 64 * (kPipeStage / 4)) col_direct(r + 4, 64 * (kPipeStage / 4), lane, 64);
+    } else if (hw == 1) {
+      uint32_t* const dst = (uint32_t*)rowslab(r + 3);
+#pragma unroll
+      for (int k = 0; k < kPipeStage; ++k) {
+        const int d = lane + 64 * k;
+        if (d < nrow) dst[d] = stg[k];
+      }
+      row_direct(r + 3, 64 * kPipeStage, lane, 64);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kPipeStage / 2; ++k)
+        if (stl[k] >= 0) lds[stl[k]] = __hiloint2double((int)stg[2 * k + 1], (int)stg[2 * k]);
+      seg_direct(S, 64 * (kPipeStage / 2), lane, 64);
     }
   };
 
@@ -1167,15 +1262,16 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
   }
   lds_barrier();
   {
-    // slabs of J_1..J_4 and I_1..I_3; raw rows of w_1, w_2, w'_2, w'_3 (direct copies)
-    for (int64_t t = 1; t <= 4; ++t) col_direct(t, 0, tid, T);
-    for (int64_t t = 1; t <= 3; ++t) row_direct(t, 0, tid, T);
-    Seg S;  // at most two segments per vector
+    // slabs of J_1..J_3 and I_1, I_2; raw rows of w_1, w_2, w'_2, w'_3 (direct copies; the next
+    // ones come through stage(-1))
+    for (int64_t t = 1; t <= 3; ++t) col_direct(t, 0, tid, T);
+    for (int64_t t = 1; t <= 2; ++t) row_direct(t, 0, tid, T);
+    Seg P;  // at most two segments per vector
     for (int v = 0; v < 4; ++v) {
-      seg_clear(S);
-      if (v < 2) segs_w(S, 1 + v);
-      else segs_wp(S, v);
-      seg_direct(S, 0, tid, T);
+      seg_clear(P);
+      if (v < 2) segs_w(P, 1 + v);
+      else segs_wp(P, v);
+      seg_direct(P, 0, tid, T);
     }
   }
   lds_barrier();
@@ -1196,11 +1292,10 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     }
     set_flag(&s_gflag, 1);
   }
+  if (tid >= 64) stage(-1);
   if (!ok) s_ok = 0;
   lds_barrier();
   if (tid < 64) {
-    load_w(W1, wr + (size_t)(1 & 1) * E, need(1, e_own), 1, 0);    // w_1 . B^0
-    load_w(W2, wpr + (size_t)(2 & 1) * E, need(2, e_own), 1, 0);   // w'_2 . B^0
     if (e_own >= 0 && need(0, e_own) && lane < kCopies) {
       unsigned long long* S0 = gs.gsum + (size_t)(1 % kGridSumRing) * kCopies * V2;
       st_tagged(S0 + (size_t)lane * V2, e_own, gat[0], 1u);
@@ -1229,11 +1324,14 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
       unsigned long long wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       spins = 0;
       while (any && ok) {
-        bool mine = true;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int q = k * 32 + (lane >> 1);
           wd[k] = ld_u64(Sg + (size_t)2 * (q < E ? q : E - 1) + p2);
+        }
+        bool mine = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
           const unsigned tg = first ? (unsigned)(wd[k] >> 32) : (unsigned)wd[k];
           mine = mine && (((needm >> k) & 1u) == 0 || tg == epB);
         }
@@ -1248,21 +1346,16 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
         vals[k] = (first && ((needm >> k) & 1u)) ? tag_value(wd[k], o) : 0.0;
       }
       if (e_own >= 0 && need(r + 1, e_own)) {
+        // w_{r+1} . B^r
+        const double d = dot_raw(wr + (size_t)((r + 1) & 1) * E, true, r + 1, r, vals);
         wait_flag(&s_gflag, (int)(r + 1));
-        double d = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) d += W1[k] * vals[k];
-        d = group_sum(d, 64);
         const double val = gat[(r + 1) & 1] + pc - d;
         if (lane < kCopies) {
           unsigned long long* Sn = gs.gsum + (size_t)((r + 2) % kGridSumRing) * kCopies * V2;
           st_tagged(Sn + (size_t)lane * V2, e_own, val, (unsigned)(r + 2));
         }
       }
-      double d2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) d2 += W2[k] * vals[k];
-      pc = -group_sum(d2, 64);
+      pc = -dot_raw(wpr + (size_t)((r + 2) & 1) * E, need(r + 2, e_own), r + 1, r, vals);  // -w'_{r+2} . B^r
       double* Bn = bv + (size_t)(r % 3) * E;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -1306,91 +1399,20 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
       last_k = a.k0 + K;
       break;
     }
-    if (tid < 64) {
-      // w_{r+2} and w'_{r+3}, both applied to B^{r+1}
-      load_w(W1, wr + (size_t)((r + 2) & 1) * E, need(r + 2, e_own), r + 2, r + 1);
-      load_w(W2, wpr + (size_t)((r + 3) & 1) * E, need(r + 3, e_own), r + 2, r + 1);
-      continue;
-    }
+    if (tid < 64) continue;
     // ---- waves 1..3: round r of the helpers
     if (tid >= 192 && filled_to < K && r + 40 > filled_to) refill(filled_to + 1, 192);
     if (filled_to < K && r + 40 > filled_to) filled_to += 64;
-    // copies for later rounds, issued now and written to LDS at the end of the round: wave 1 the
-    // column slab of J_{r+5} (16-byte chunks), wave 2 the row slab of I_{r+4} (dwords), wave 3 the
-    // raw rows of w_{r+3} and w'_{r+4} (doubles)
-    uint32_t stg[kPipeStage];
-    int stl[kPipeStage / 2];
-    const int hw = (tid >> 6) - 1;
-    int ncol = 0, nrow = 0;
-    Seg S;
-    seg_clear(S);
-#pragma unroll
-    for (int k = 0; k < kPipeStage / 2; ++k) stl[k] = -1;
-    if (hw == 0) {
-      const int64_t t = r + 5;
-      ncol = nr > 0 ? nJ_of(t) * c16 : 0;
-      if (ncol > 0) {
-        const char* src = colsrc(t);
-        const int64_t cstride = a.ldc * esz;
-        const int dbase = (int)((const uint32_t*)colslab(t) - (const uint32_t*)lds);
-        int c = lane / c16, p = lane - c * c16;
-        const int sc = 64 / c16, sp = 64 - sc * c16;
-#pragma unroll
-        for (int k = 0; k < kPipeStage / 4; ++k) {
-          const int d = lane + 64 * k;
-          if (d < ncol) {
-            const u32x4 v = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
-            stg[4 * k] = v.x;
-            stg[4 * k + 1] = v.y;
-            stg[4 * k + 2] = v.z;
-            stg[4 * k + 3] = v.w;
-            stl[k] = dbase + 4 * (c * c16 + p);
-          }
-          p += sp;
-          c += sc;
-          if (p >= c16) {
-            p -= c16;
-            ++c;
-          }
-        }
-      }
-    } else if (hw == 1) {
-      nrow = row_dwords(r + 4);
-      if (nrow > 0) {
-        gdword* src = (gdword*)rowsrc(r + 4);
-#pragma unroll
-        for (int k = 0; k < kPipeStage; ++k) {
-          const int d = lane + 64 * k;
-          if (d < nrow) stg[k] = src[d];
-        }
-      }
-    } else {
-      segs_w(S, r + 3);
-      segs_wp(S, r + 4);
-      const int tot = S.l0 + S.l1 + S.l2 + S.l3;
-#pragma unroll
-      for (int k = 0; k < kPipeStage / 2; ++k) {
-        const int d = lane + 64 * k;
-        if (d < tot) {
-          const double* src;
-          double* dst;
-          seg_at(S, d, src, dst);
-          const double v = *(gdouble*)src;
-          stg[2 * k] = (uint32_t)__double2loint(v);
-          stg[2 * k + 1] = (uint32_t)__double2hiint(v);
-          stl[k] = (int)(dst - lds);
-        }
-      }
-    }
+    commit(r);  // the copies the previous round left in flight land in LDS
     const int64_t tz = r + 1 <= K ? r + 1 : K, tx = r <= K ? r : K;
     const double* zc = zh + (size_t)(tz & 3) * L.NR;
     const double* xc = xh + (size_t)(tx & 3) * L.NC;
-    if (tid < 128) {
+    if (hw == 0) {
       // wave 1: z^{r+1}, then the v entries of round r + 3 from it
       if (r + 1 <= K && nr > 0) zstep(r + 1, Bc);
       set_flag(&s_zflag, (int)(r + 1));
       part_v(r + 3, zc);
-    } else if (tid < 192) {
+    } else if (hw == 1) {
       // wave 2: x^r, then the u entries (and the error) of round r + 3
       if (r >= 1 && r <= K && nc > 0) xstep(r, Bc + MJ);
       part_u(r + 3, xc, zc, (int)(r + 1));
@@ -1402,27 +1424,7 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
       }
       set_flag(&s_gflag, (int)(r + 2));
     }
-    // the staged copies land in LDS; what did not fit is copied directly
-    if (hw == 0) {
-      uint32_t* const ldw = (uint32_t*)lds;
-#pragma unroll
-      for (int k = 0; k < kPipeStage / 4; ++k)
-        if (stl[k] >= 0) *(u32x4*)(ldw + stl[k]) = u32x4{stg[4 * k], stg[4 * k + 1], stg[4 * k + 2], stg[4 * k + 3]};
-      if (ncol > 64 * (kPipeStage / 4)) col_direct(r + 5, 64 * (kPipeStage / 4), lane, 64);
-    } else if (hw == 1) {
-      uint32_t* const dst = (uint32_t*)rowslab(r + 4);
-#pragma unroll
-      for (int k = 0; k < kPipeStage; ++k) {
-        const int d = lane + 64 * k;
-        if (d < nrow) dst[d] = stg[k];
-      }
-      row_direct(r + 4, 64 * kPipeStage, lane, 64);
-    } else {
-#pragma unroll
-      for (int k = 0; k < kPipeStage / 2; ++k)
-        if (stl[k] >= 0) lds[stl[k]] = __hiloint2double((int)stg[2 * k + 1], (int)stg[2 * k]);
-      seg_direct(S, 64 * (kPipeStage / 2), lane, 64);
-    }
+    stage(r);  // loads for the next round, in flight across the wait for the broadcast
   }
   wait_mem();
   if (alive && !final_err) {  // x^K, z^K
