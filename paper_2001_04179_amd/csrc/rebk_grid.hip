@@ -788,12 +788,26 @@ __device__ __forceinline__ double dot_strided(const TP* a, int sa, const double*
     s2 += widen(av[6]) * bv[6];
     s3 += widen(av[7]) * bv[7];
   }
+  if (i + 3 < cnt) {
+    TP av[4];
+    double bv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      av[k] = a[(i + k) * sa];
+      bv[k] = b[(i + k) * sb];
+    }
+    s0 += widen(av[0]) * bv[0];
+    s1 += widen(av[1]) * bv[1];
+    s2 += widen(av[2]) * bv[2];
+    s3 += widen(av[3]) * bv[3];
+    i += 4;
+  }
   for (; i < cnt; ++i) s0 += widen(a[i * sa]) * b[i * sb];
   return (s0 + s1) + (s2 + s3);
 }
 
 template <typename TP>
-__global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, GridSync gs,
+__global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, GridSync gs,
                                                                   const double* __restrict__ Gm,
                                                                   const double* __restrict__ Hm,
                                                                   const double* __restrict__ Arm) {
@@ -802,9 +816,13 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
   __shared__ int64_t s_c0[kRing], s_r0[kRing];
   __shared__ double s_cc[kRing], s_cr[kRing];
   __shared__ int s_ok;
-  __shared__ int s_zflag;  // z^t of the owned rows is in LDS for t <= s_zflag
-  __shared__ int s_gflag;  // the owner's gathered sum of round t is in LDS for t <= s_gflag
+  // handshakes between the waves (values are round or iteration numbers, nondecreasing)
+  __shared__ int s_zflag[2];  // z^t of the owned rows, half h, is in LDS for t <= s_zflag[h]
+  __shared__ int s_xflag[2];  // x^t of the owned columns, half h, is in LDS for t <= s_xflag[h]
+  __shared__ int s_gflag;     // the owner's gathered sum of round t is in LDS for t <= s_gflag
   const int G = gridDim.x, w = blockIdx.x, tid = threadIdx.x, T = blockDim.x, lane = tid & 63;
+  const int wv = tid >> 6;  // wave: 0 broadcast; 1, 2 the z side; 5, 6 the x side; 3 gathers;
+                            // 3, 4 and 7 copy slabs and rows (waves w and w + 4 share a SIMD)
   const int64_t m = a.m, n = a.n;
   const int MJ = a.max_nJ, MI = a.max_nI, E = gs.stride;
   const int esz = (int)sizeof(TP);
@@ -1056,14 +1074,14 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
   // ---- partial sums of round t from z (owned rows) and x (owned columns):
   //   v entries A_{J_{t+1}}^T z over owned rows (one wave), u entries A_{I_t} x - b + z (one wave),
   //   and ||x - x_ref||^2 when due (the u wave)
-  auto part_v = [&](int64_t t, const double* zc) {  // whole wave
+  auto part_v = [&](int64_t t, const double* zc, int c_lo, int c_hi) {  // columns [c_lo, c_hi), whole wave
     unsigned long long* P = gs.part + ((size_t)(t & (kPipeParts - 1)) * G + w) * V2;
     const unsigned ep = (unsigned)(t + 1);
-    const int nJn = nJ_of(t + 1);
-    if (nJn == 0) return;
+    const int nJn = c_hi < nJ_of(t + 1) ? c_hi : nJ_of(t + 1);
+    if (nJn <= c_lo) return;
     const TP* Sl = colslab(t + 1);
-    const int tq = lanes_per_item(64, nJn), per = 64 / tq, sub = lane % tq;
-    for (int c0 = 0; c0 < nJn; c0 += per) {
+    const int tq = lanes_per_item(64, nJn - c_lo), per = 64 / tq, sub = lane % tq;
+    for (int c0 = c_lo; c0 < nJn; c0 += per) {
       const int c = c0 + lane / tq;
       const TP* col = Sl + (size_t)(c < nJn ? c : nJn - 1) * nrs;
       const int cnt = sub < nr ? (nr - sub + tq - 1) / tq : 0;
@@ -1071,31 +1089,33 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
       if (c < nJn && sub == 0) st_tagged(P, c, acc, ep);
     }
   };
-  auto part_u = [&](int64_t t, const double* xc, const double* zc, int zready) {  // whole wave
+  // rows [l_lo, l_hi) of I_t (whole wave); with_err: also ||x - x_ref||^2 when due
+  auto part_u = [&](int64_t t, const double* xc, const double* zc, int zready, int l_lo, int l_hi, bool with_err) {
     unsigned long long* P = gs.part + ((size_t)(t & (kPipeParts - 1)) * G + w) * V2;
     const unsigned ep = (unsigned)(t + 1);
-    const int nIt = nI_of(t);
-    if (nIt > 0) {
+    const int nIt = nI_of(t), lend = l_hi < nIt ? l_hi : nIt;
+    if (lend > l_lo) {
       const TP* Sr = rowslab(t);
       const int64_t rI = s_r0[slot(t)];
       bool waited = false;
-      for (int l0 = 0; l0 < nIt; l0 += 64) {
+      for (int l0 = l_lo; l0 < lend; l0 += 64) {
         const int l = l0 + lane;
-        double acc = l < nIt ? dot_strided(Sr + l, nIt, xc, 1, nc) : 0.0;
-        // owned rows of I_t add z - b (z from the other wave: wait for it once)
-        const int64_t lo = rI + l0, hi = rI + (l0 + 64 < nIt ? l0 + 64 : nIt);
+        double acc = l < lend ? dot_strided(Sr + l, nIt, xc, 1, nc) : 0.0;
+        // owned rows of I_t add z - b (z from the z-side waves: wait for it once)
+        const int64_t lo = rI + l0, hi = rI + (l0 + 64 < lend ? l0 + 64 : lend);
         if (lo < r1 && hi > r0) {
           if (!waited) {
-            wait_flag(&s_zflag, zready);
+            wait_flag(&s_zflag[0], zready);
+            wait_flag(&s_zflag[1], zready);
             waited = true;
           }
           const int64_t gl = rI + l;
-          if (l < nIt && gl >= r0 && gl < r1) acc += zc[gl - r0] - bl[gl - r0];
+          if (l < lend && gl >= r0 && gl < r1) acc += zc[gl - r0] - bl[gl - r0];
         }
-        if (l < nIt) st_tagged(P, MJ + l, acc, ep);
+        if (l < lend) st_tagged(P, MJ + l, acc, ep);
       }
     }
-    if (err_round(t)) {
+    if (with_err && err_round(t)) {
       double e = 0.0;
       for (int cc = lane; cc < nc; cc += 64) {
         const double d = xc[cc] - xr[cc];
@@ -1108,148 +1128,123 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     }
   };
   // z^t = z^{t-1} - c'_t A_{J_t} v^t on owned rows (one wave), v^t = B^{t-1}[0, nJ)
-  auto zstep = [&](int64_t t, const double* vB) {
+  auto zstep = [&](int64_t t, const double* vB, int p_lo, int p_hi) {  // owned rows [p_lo, p_hi)
     const int nJ = nJ_of(t);
     const TP* Sl = colslab(t);
     const double coef = cc_of(t);
     const double* zo = zh + (size_t)((t - 1) & 3) * L.NR;
     double* zn = zh + (size_t)(t & 3) * L.NR;
-    for (int p = lane; p < nr; p += 64) zn[p] = zo[p] - coef * dot_strided(Sl + p, nrs, vB, 1, nJ);
+    for (int p = p_lo + lane; p < p_hi; p += 64) zn[p] = zo[p] - coef * dot_strided(Sl + p, nrs, vB, 1, nJ);
   };
   // x^t = x^{t-1} - c_t A_{I_t}^T u^t on owned columns (one wave), u^t = B^t[MJ, MJ + nI)
-  auto xstep = [&](int64_t t, const double* uB) {
+  auto xstep = [&](int64_t t, const double* uB, int c_lo, int c_hi) {  // owned columns [c_lo, c_hi)
+    if (c_hi <= c_lo) return;
     const int nI = nI_of(t);
     const TP* Sl = rowslab(t);
     const double coef = cr_of(t);
     const double* xo = xh + (size_t)((t - 1) & 3) * L.NC;
     double* xn = xh + (size_t)(t & 3) * L.NC;
-    const int tpc = lanes_per_item(64, nc), cp = 64 / tpc, sub = lane % tpc;
-    for (int c0 = 0; c0 < nc; c0 += cp) {
+    const int tpc = lanes_per_item(64, c_hi - c_lo), cp = 64 / tpc, sub = lane % tpc;
+    for (int c0 = c_lo; c0 < c_hi; c0 += cp) {
       const int cc = c0 + lane / tpc;
-      const TP* col = Sl + (size_t)(cc < nc ? cc : nc - 1) * nI;
+      const TP* col = Sl + (size_t)(cc < c_hi ? cc : c_hi - 1) * nI;
       const int cnt = sub < nI ? (nI - sub + tpc - 1) / tpc : 0;
       const double acc = group_sum(dot_strided(col + sub, tpc, uB + sub, tpc, cnt), tpc);
-      if (cc < nc && sub == 0) xn[cc] = xo[cc] - coef * acc;
+      if (cc < c_hi && sub == 0) xn[cc] = xo[cc] - coef * acc;
     }
   };
 
   // ---- wave 0: the broadcast (8 entries per lane pair: entry q = 32 k + lane / 2, first lanes)
-  double pc = 0.0;  // -w'_{r+1} . B^{r-1} of this workgroup's entry
-  // (scaled raw rows) . vals over the wave: the v part scaled by c'_{tv} over nJ(tv) entries, the u
-  // part by c_{tu} over nI(tu) entries (u owners only); vals hold a broadcast vector in the
-  // 32 k + lane / 2 layout (first lanes)
-  auto dot_raw = [&](const double* raw, bool has, int64_t tv, int64_t tu, const double* vals) -> double {
+  double pc = 0.0;  // -w'_{r+1} . B^{r-1} of this workgroup's entry (wave 0)
+  // Scaled coefficient vector in the layout of wave 0's poll (entry 32 k + lane / 2 in register k
+  // of the first lane of each pair) from raw rows in LDS: the v part scaled by c'_{tv} over
+  // nJ(tv) entries, the u part by c_{tu} over nI(tu) entries (u owners only), zero elsewhere.
+  auto load_w = [&](double* Wv, const double* raw, bool has, int64_t tv, int64_t tu) {
     const int nv = has && (v_owner || u_owner) ? nJ_of(tv) : 0;
     const int nu = has && u_owner ? nI_of(tu) : 0;
     const double cv = cc_of(tv), cu = cr_of(tu);
-    double d = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int q = k * 32 + (lane >> 1);
       const bool inv = first && q < nv, inu = first && q >= MJ && q - MJ < nu;
       const double rw = (inv || inu) ? raw[q] : 0.0;
-      d += ((inv ? cv : cu) * rw) * vals[k];
+      Wv[k] = (inv ? cv : cu) * rw;
     }
-    return group_sum(d, 64);
   };
 
-  // Copies in flight from one round to the next (helper waves; wave hw + 1): stage(r) issues the
-  // loads for round r + 1 (wave 1 the column slab of J_{r+5} in 16-byte chunks, wave 2 the row slab
-  // of I_{r+4} in dwords, wave 3 the raw rows of w_{r+4} and w'_{r+5} in doubles), left in flight
-  // across the wait for the broadcast; commit(r + 1) writes them to LDS and copies directly what
-  // did not fit.
-  const int hw = (tid >> 6) - 1;
-  uint32_t stg[kPipeStage];
-  int stl[kPipeStage / 2];
-  int ncol = 0, nrow = 0;
-  Seg S;
-  seg_clear(S);
+  // Copies for later rounds, one wave each (all loads issued before any is written to LDS; the
+  // waves have nothing else on their path until the round's end): the column slab of J_t in
+  // 16-byte chunks, the row slab of I_t in dwords, the raw rows of w_t and w'_{t+1} in doubles.
+  auto copy_col = [&](int64_t t) {
+    const int ncol = nr > 0 ? nJ_of(t) * c16 : 0;
+    if (ncol == 0) return;
+    const char* src = colsrc(t);
+    const int64_t cstride = a.ldc * esz;
+    u32x4* const dst = (u32x4*)colslab(t);
+    u32x4 v[kPipeStage / 4];
+    int at[kPipeStage / 4];
+    int c = lane / c16, p = lane - c * c16;
+    const int sc = 64 / c16, sp = 64 - sc * c16;
 #pragma unroll
-  for (int k = 0; k < kPipeStage / 2; ++k) stl[k] = -1;
-  auto stage = [&](int64_t r) {
-#pragma unroll
-    for (int k = 0; k < kPipeStage / 2; ++k) stl[k] = -1;
-    ncol = 0;
-    nrow = 0;
-    seg_clear(S);
-    if (hw == 0) {
-      const int64_t t = r + 5;
-      ncol = nr > 0 ? nJ_of(t) * c16 : 0;
-      if (ncol > 0) {
-        const char* src = colsrc(t);
-        const int64_t cstride = a.ldc * esz;
-        const int dbase = (int)((const uint32_t*)colslab(t) - (const uint32_t*)lds);
-        int c = lane / c16, p = lane - c * c16;
-        const int sc = 64 / c16, sp = 64 - sc * c16;
-#pragma unroll
-        for (int k = 0; k < kPipeStage / 4; ++k) {
-          const int d = lane + 64 * k;
-          if (d < ncol) {
-            const u32x4 v = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
-            stg[4 * k] = v.x;
-            stg[4 * k + 1] = v.y;
-            stg[4 * k + 2] = v.z;
-            stg[4 * k + 3] = v.w;
-            stl[k] = dbase + 4 * (c * c16 + p);
-          }
-          p += sp;
-          c += sc;
-          if (p >= c16) {
-            p -= c16;
-            ++c;
-          }
-        }
+    for (int k = 0; k < kPipeStage / 4; ++k) {
+      at[k] = -1;
+      if (lane + 64 * k < ncol) {
+        v[k] = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
+        at[k] = c * c16 + p;
       }
-    } else if (hw == 1) {
-      nrow = row_dwords(r + 4);
-      if (nrow > 0) {
-        gdword* src = (gdword*)rowsrc(r + 4);
-#pragma unroll
-        for (int k = 0; k < kPipeStage; ++k) {
-          const int d = lane + 64 * k;
-          if (d < nrow) stg[k] = src[d];
-        }
-      }
-    } else {
-      segs_w(S, r + 4);
-      segs_wp(S, r + 5);
-      const int tot = S.l0 + S.l1 + S.l2 + S.l3;
-#pragma unroll
-      for (int k = 0; k < kPipeStage / 2; ++k) {
-        const int d = lane + 64 * k;
-        if (d < tot) {
-          const double* src;
-          double* dst;
-          seg_at(S, d, src, dst);
-          const double v = *(gdouble*)src;
-          stg[2 * k] = (uint32_t)__double2loint(v);
-          stg[2 * k + 1] = (uint32_t)__double2hiint(v);
-          stl[k] = (int)(dst - lds);
-        }
+      p += sp;
+      c += sc;
+      if (p >= c16) {
+        p -= c16;
+        ++c;
       }
     }
+#pragma unroll
+    for (int k = 0; k < kPipeStage / 4; ++k)
+      if (at[k] >= 0) dst[at[k]] = v[k];
+    if (ncol > 64 * (kPipeStage / 4)) col_direct(t, 64 * (kPipeStage / 4), lane, 64);
   };
-  auto commit = [&](int64_t r) {
-    if (hw == 0) {
-      uint32_t* const ldw = (uint32_t*)lds;
+  auto copy_row = [&](int64_t t, auto&& between) {  // `between` runs while the loads are in flight
+    const int nrow = row_dwords(t);
+    uint32_t v[kPipeStage];
+    if (nrow > 0) {
+      gdword* src = (gdword*)rowsrc(t);
 #pragma unroll
-      for (int k = 0; k < kPipeStage / 4; ++k)
-        if (stl[k] >= 0) *(u32x4*)(ldw + stl[k]) = u32x4{stg[4 * k], stg[4 * k + 1], stg[4 * k + 2], stg[4 * k + 3]};
-      if (ncol > 64 * (kPipeStage / 4)) col_direct(r + 4, 64 * (kPipeStage / 4), lane, 64);
-    } else if (hw == 1) {
-      uint32_t* const dst = (uint32_t*)rowslab(r + 3);
-#pragma unroll
-      for (int k = 0; k < kPipeStage; ++k) {
-        const int d = lane + 64 * k;
-        if (d < nrow) dst[d] = stg[k];
-      }
-      row_direct(r + 3, 64 * kPipeStage, lane, 64);
-    } else {
-#pragma unroll
-      for (int k = 0; k < kPipeStage / 2; ++k)
-        if (stl[k] >= 0) lds[stl[k]] = __hiloint2double((int)stg[2 * k + 1], (int)stg[2 * k]);
-      seg_direct(S, 64 * (kPipeStage / 2), lane, 64);
+      for (int k = 0; k < kPipeStage; ++k)
+        if (lane + 64 * k < nrow) v[k] = src[lane + 64 * k];
     }
+    between();
+    if (nrow > 0) {
+      uint32_t* const dst = (uint32_t*)rowslab(t);
+#pragma unroll
+      for (int k = 0; k < kPipeStage; ++k)
+        if (lane + 64 * k < nrow) dst[lane + 64 * k] = v[k];
+    }
+    row_direct(t, 64 * kPipeStage, lane, 64);
+  };
+  auto copy_w = [&](int64_t t) {  // w_t and w'_{t+1}
+    Seg S;
+    seg_clear(S);
+    segs_w(S, t);
+    segs_wp(S, t + 1);
+    const int tot = S.l0 + S.l1 + S.l2 + S.l3;
+    double v[kPipeStage / 2];
+    int at[kPipeStage / 2];
+#pragma unroll
+    for (int k = 0; k < kPipeStage / 2; ++k) {
+      at[k] = -1;
+      if (lane + 64 * k < tot) {
+        const double* src;
+        double* dst;
+        seg_at(S, lane + 64 * k, src, dst);
+        v[k] = *(gdouble*)src;
+        at[k] = (int)(dst - lds);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPipeStage / 2; ++k)
+      if (at[k] >= 0) lds[at[k]] = v[k];
+    seg_direct(S, 64 * (kPipeStage / 2), lane, 64);
   };
 
   // ---------------- prologue
@@ -1257,15 +1252,15 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
   int64_t filled_to = 128;
   if (tid == 0) {
     s_ok = 1;
-    s_zflag = 0;
+    s_zflag[0] = s_zflag[1] = 0;
+    s_xflag[0] = s_xflag[1] = 0;
     s_gflag = -1;
   }
   lds_barrier();
   {
-    // slabs of J_1..J_3 and I_1, I_2; raw rows of w_1, w_2, w'_2, w'_3 (direct copies; the next
-    // ones come through stage(-1))
-    for (int64_t t = 1; t <= 3; ++t) col_direct(t, 0, tid, T);
-    for (int64_t t = 1; t <= 2; ++t) row_direct(t, 0, tid, T);
+    // slabs of J_1..J_4 and I_1..I_3; raw rows of w_1, w_2, w'_2, w'_3 (direct copies)
+    for (int64_t t = 1; t <= 4; ++t) col_direct(t, 0, tid, T);
+    for (int64_t t = 1; t <= 3; ++t) row_direct(t, 0, tid, T);
     Seg P;  // at most two segments per vector
     for (int v = 0; v < 4; ++v) {
       seg_clear(P);
@@ -1276,14 +1271,14 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
   }
   lds_barrier();
   // partial sums of rounds 0, 1, 2 from x^0, z^0; the owner gathers rounds 0 and 1
-  if (tid >= 64 && tid < 128) {
-    part_v(0, zh);
-    part_v(1, zh);
-    part_v(2, zh);
-  } else if (tid >= 128 && tid < 192) {
-    part_u(1, xh, zh, 0);
-    part_u(2, xh, zh, 0);
-  } else if (tid >= 192) {
+  if (wv == 1) {
+    part_v(0, zh, 0, MJ);
+    part_v(1, zh, 0, MJ);
+    part_v(2, zh, 0, MJ);
+  } else if (wv == 5) {
+    part_u(1, xh, zh, 0, 0, MI, true);
+    part_u(2, xh, zh, 0, 0, MI, true);
+  } else if (wv == 3) {
     const double g0 = need(0, e_own) ? gather(0, e_own) : 0.0;
     const double g1 = need(1, e_own) ? gather(1, e_own) : 0.0;
     if (lane == 0) {
@@ -1292,7 +1287,6 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
     }
     set_flag(&s_gflag, 1);
   }
-  if (tid >= 64) stage(-1);
   if (!ok) s_ok = 0;
   lds_barrier();
   if (tid < 64) {
@@ -1307,10 +1301,39 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
   double last_err2 = -1.0;
   int64_t last_check = -1;
   bool alive = s_ok != 0;
-  int64_t r = 0;
-  for (; alive; ++r) {
-    if (tid < 64) {
-      // ---- wave 0: poll B^r, publish this workgroup's entry of B^{r+1}, hand B^r over
+  // After the workgroup barrier of round r (B^r in LDS): the stop rule on the error B^r carries,
+  // the same decision in every wave.  Returns true when the solve ends here (outputs written).
+  auto round_end = [&](int64_t r) -> bool {
+    if (tid == 0 && w == 0 && a.trace_j && r >= 1 && r <= K) {
+      a.trace_j[r - 1] = s_j[slot(r)];
+      a.trace_i[r - 1] = s_i[slot(r)];
+    }
+    if (!err_round(r)) return false;
+    const double e2 = bv[(size_t)(r % 3) * E + err_slot];  // the error of x^{r-3}
+    const int64_t k = r - 3;
+    last_err2 = e2;
+    last_check = a.k0 + k;
+    const double rel = sqrt(e2) / sqrt(a.xref_sq);
+    const bool stop = checking && (rel < a.tol || !isfinite(e2) || rel > 1e6);
+    if (!stop && k != K) return false;
+    stopped = stop ? 1 : 0;
+    status = !checking ? 0 : (rel < a.tol ? 0 : ((!isfinite(e2) || rel > 1e6) ? 2 : 1));
+    last_k = a.k0 + k;
+    const double* zk = zh + (size_t)(k & 3) * L.NR;
+    const double* xk = xh + (size_t)(k & 3) * L.NC;
+    for (int p = tid; p < nr; p += T)
+      if (a.z_out) a.z_out[r0 + p] = zk[p];
+    for (int p = tid; p < nc; p += T) a.x_out[cA + p] = xk[p];
+    return true;
+  };
+
+  if (tid < 64) {
+    // ---- wave 0: poll B^r, publish this workgroup's entry of B^{r+1}, hand B^r over.  W1 and W2
+    // hold w_{r+1} and w'_{r+2} of this workgroup's entry, scaled, in the layout of the poll.
+    double W1[8], W2[8];
+    load_w(W1, wr + (size_t)(1 & 1) * E, need(1, e_own), 1, 0);
+    load_w(W2, wpr + (size_t)(2 & 1) * E, need(2, e_own), 1, 0);
+    for (int64_t r = 0; alive; ++r) {
       const unsigned epB = (unsigned)(r + 1);
       const unsigned long long* Sg =
           gs.gsum + (size_t)(epB % kGridSumRing) * kCopies * V2 + (size_t)(w % kCopies) * V2;
@@ -1321,6 +1344,10 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
         if (q < E && need(r, q)) needm |= 1u << k;
       }
       const bool any = __any(needm != 0);
+      const bool publish = e_own >= 0 && need(r + 1, e_own);
+      // the gathered sum of round r + 1, if the helpers have it already
+      const bool early = publish && __hip_atomic_load(&s_gflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= r + 1;
+      double g = early ? gat[(r + 1) & 1] : 0.0;
       unsigned long long wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       spins = 0;
       while (any && ok) {
@@ -1341,90 +1368,102 @@ __global__ void __launch_bounds__(kGridThreads) pipe_solve_kernel(SolveArgs a, G
       double vals[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int q = k * 32 + (lane >> 1);
         const unsigned long long o = mirror_word(wd[k]);
         vals[k] = (first && ((needm >> k) & 1u)) ? tag_value(wd[k], o) : 0.0;
       }
-      if (e_own >= 0 && need(r + 1, e_own)) {
-        // w_{r+1} . B^r
-        const double d = dot_raw(wr + (size_t)((r + 1) & 1) * E, true, r + 1, r, vals);
-        wait_flag(&s_gflag, (int)(r + 1));
-        const double val = gat[(r + 1) & 1] + pc - d;
+      if (publish) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d += W1[k] * vals[k];  // w_{r+1} . B^r
+        d = group_sum(d, 64);
+        if (!early) {
+          wait_flag(&s_gflag, (int)(r + 1));
+          g = gat[(r + 1) & 1];
+        }
         if (lane < kCopies) {
           unsigned long long* Sn = gs.gsum + (size_t)((r + 2) % kGridSumRing) * kCopies * V2;
-          st_tagged(Sn + (size_t)lane * V2, e_own, val, (unsigned)(r + 2));
+          st_tagged(Sn + (size_t)lane * V2, e_own, g + pc - d, (unsigned)(r + 2));
         }
       }
-      pc = -dot_raw(wpr + (size_t)((r + 2) & 1) * E, need(r + 2, e_own), r + 1, r, vals);  // -w'_{r+2} . B^r
+      double d2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) d2 += W2[k] * vals[k];  // w'_{r+2} . B^r
+      pc = -group_sum(d2, 64);
       double* Bn = bv + (size_t)(r % 3) * E;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const int q = k * 32 + (lane >> 1);
         if (first && q < E) Bn[q] = vals[k];
       }
-    }
-    if (!ok) s_ok = 0;
-    lds_barrier();  // B^r in LDS; the helpers' work of round r - 1 is done
-    if (s_ok == 0) {
-      alive = false;
-      break;
-    }
-    if (tid == 0 && w == 0 && a.trace_j && r >= 1 && r <= K) {
-      a.trace_j[r - 1] = s_j[slot(r)];
-      a.trace_i[r - 1] = s_i[slot(r)];
-    }
-    const double* Bc = bv + (size_t)(r % 3) * E;
-    if (err_round(r)) {  // the error of x^{r-3}
-      const double e2 = Bc[err_slot];
-      const int64_t k = r - 3;
-      last_err2 = e2;
-      last_check = a.k0 + k;
-      const double rel = sqrt(e2) / sqrt(a.xref_sq);
-      const bool stop = checking && (rel < a.tol || !isfinite(e2) || rel > 1e6);
-      if (stop || k == K) {
-        stopped = stop ? 1 : 0;
-        status = !checking ? 0 : (rel < a.tol ? 0 : ((!isfinite(e2) || rel > 1e6) ? 2 : 1));
-        last_k = a.k0 + k;
-        const double* zk = zh + (size_t)(k & 3) * L.NR;
-        const double* xk = xh + (size_t)(k & 3) * L.NC;
-        for (int p = tid; p < nr; p += T)
-          if (a.z_out) a.z_out[r0 + p] = zk[p];
-        for (int p = tid; p < nc; p += T) a.x_out[cA + p] = xk[p];
+      if (!ok) s_ok = 0;
+      lds_barrier();  // B^r in LDS; the helpers' work of round r - 1 is done
+      if (s_ok == 0) {
+        alive = false;
         break;
       }
-    }
-    if (!final_err && r == K) {  // the last step: x^K (z^K was formed one round earlier)
-      if (tid >= 128 && tid < 192 && nc > 0) xstep(K, Bc + MJ);
-      lds_barrier();
-      last_k = a.k0 + K;
-      break;
-    }
-    if (tid < 64) continue;
-    // ---- waves 1..3: round r of the helpers
-    if (tid >= 192 && filled_to < K && r + 40 > filled_to) refill(filled_to + 1, 192);
-    if (filled_to < K && r + 40 > filled_to) filled_to += 64;
-    commit(r);  // the copies the previous round left in flight land in LDS
-    const int64_t tz = r + 1 <= K ? r + 1 : K, tx = r <= K ? r : K;
-    const double* zc = zh + (size_t)(tz & 3) * L.NR;
-    const double* xc = xh + (size_t)(tx & 3) * L.NC;
-    if (hw == 0) {
-      // wave 1: z^{r+1}, then the v entries of round r + 3 from it
-      if (r + 1 <= K && nr > 0) zstep(r + 1, Bc);
-      set_flag(&s_zflag, (int)(r + 1));
-      part_v(r + 3, zc);
-    } else if (hw == 1) {
-      // wave 2: x^r, then the u entries (and the error) of round r + 3
-      if (r >= 1 && r <= K && nc > 0) xstep(r, Bc + MJ);
-      part_u(r + 3, xc, zc, (int)(r + 1));
-    } else {
-      // wave 3: the owner's sum of round r + 2
-      if (need(r + 2, e_own)) {
-        const double g = gather(r + 2, e_own);
-        if (lane == 0) gat[(r + 2) & 1] = g;
+      if (round_end(r)) break;
+      if (!final_err && r == K) {
+        lds_barrier();
+        last_k = a.k0 + K;
+        break;
       }
-      set_flag(&s_gflag, (int)(r + 2));
+      // w_{r+2} and w'_{r+3}, both applied to B^{r+1}
+      load_w(W1, wr + (size_t)((r + 2) & 1) * E, need(r + 2, e_own), r + 2, r + 1);
+      load_w(W2, wpr + (size_t)((r + 3) & 1) * E, need(r + 3, e_own), r + 2, r + 1);
     }
-    stage(r);  // loads for the next round, in flight across the wait for the broadcast
+  } else {
+    // ---- waves 1..3: round r of the helpers, after B^r is in LDS
+    for (int64_t r = 0; alive; ++r) {
+      if (!ok) s_ok = 0;
+      lds_barrier();
+      if (s_ok == 0) {
+        alive = false;
+        break;
+      }
+      if (round_end(r)) break;
+      const double* Bc = bv + (size_t)(r % 3) * E;
+      if (!final_err && r == K) {  // the last step: x^K (z^K was formed one round earlier)
+        if (wv == 5 && nc > 0) xstep(K, Bc + MJ, 0, nc);
+        lds_barrier();
+        last_k = a.k0 + K;
+        break;
+      }
+      if (wv == 7 && filled_to < K && r + 40 > filled_to) refill(filled_to + 1, 448);
+      if (filled_to < K && r + 40 > filled_to) filled_to += 64;
+      const int64_t tz = r + 1 <= K ? r + 1 : K, tx = r <= K ? r : K;
+      const double* zc = zh + (size_t)(tz & 3) * L.NR;
+      const double* xc = xh + (size_t)(tx & 3) * L.NC;
+      if (wv == 1 || wv == 2) {
+        // z side, half h: z^{r+1} on half the owned rows, then half the v entries of round r + 3
+        const int h = wv - 1, ph = (nr + 1) / 2;
+        if (r + 1 <= K && nr > 0) zstep(r + 1, Bc, h == 0 ? 0 : ph, h == 0 ? ph : nr);
+        set_flag(&s_zflag[h], (int)(r + 1));
+        wait_flag(&s_zflag[1 - h], (int)(r + 1));
+        const int nJn = nJ_of(r + 4), ch = (nJn + 1) / 2;
+        part_v(r + 3, zc, h == 0 ? 0 : ch, h == 0 ? ch : nJn);
+      } else if (wv == 5 || wv == 6) {
+        // x side, half h: x^r on half the owned columns, then half the u entries of round r + 3
+        const int h = wv - 5, chx = (nc + 1) / 2;
+        if (r >= 1 && r <= K && nc > 0) xstep(r, Bc + MJ, h == 0 ? 0 : chx, h == 0 ? chx : nc);
+        set_flag(&s_xflag[h], (int)r);
+        wait_flag(&s_xflag[1 - h], (int)r);
+        const int nIt = nI_of(r + 3), lh = (nIt + 1) / 2;
+        part_u(r + 3, xc, zc, (int)(r + 1), h == 0 ? 0 : lh, h == 0 ? lh : nIt, h == 0);
+      } else if (wv == 3) {
+        // the owner's sum of round r + 2 (wave 0 needs it for its next entry), then the column
+        // slab of J_{r+5}
+        if (need(r + 2, e_own)) {
+          const double g = gather(r + 2, e_own);
+          if (lane == 0) gat[(r + 2) & 1] = g;
+        }
+        set_flag(&s_gflag, (int)(r + 2));
+        copy_col(r + 5);
+      } else if (wv == 4) {
+        copy_row(r + 4, []() {});  // the row slab of I_{r+4}
+      } else if (wv == 7) {
+        copy_w(r + 3);  // the raw rows of w_{r+3} and w'_{r+4}
+      }
+    }
   }
   wait_mem();
   if (alive && !final_err) {  // x^K, z^K
@@ -1514,7 +1553,7 @@ hipError_t pipe_solve_max_blocks(int panel_dtype, size_t lds_bytes, int* blocks_
     const void* k = (const void*)pipe_solve_kernel<TP>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kGridThreads, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kPipeThreads, lds_bytes);
   });
 }
 
@@ -1542,7 +1581,7 @@ hipError_t launch_pipe_solve(const SolveArgs& a, const GridSync& gs, const doubl
     const double* h = Hm;
     const double* ar = Arm;
     void* args[] = {&aa, &gg, (void*)&g, (void*)&h, (void*)&ar};
-    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kGridThreads), args, (unsigned)lds, st);
+    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kPipeThreads), args, (unsigned)lds, st);
   });
 }
 

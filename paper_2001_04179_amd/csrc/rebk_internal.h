@@ -150,6 +150,7 @@ hipError_t grid_solve_max_blocks(int panel_dtype, size_t lds_bytes, bool row_lds
 // row-major (m x n), all FP64 from the stored panel values; GridSync.part holds 4 x grid vectors.
 // Its broadcast vector has at most kPipeMaxStride entries (8 registers per lane of one wave).
 constexpr int kPipeMaxStride = 256;
+constexpr int kPipeThreads = 512;  // eight waves: the broadcast, two per update, a gather, two copiers
 hipError_t launch_pipe_solve(const SolveArgs& a, const GridSync& gs, const double* Gm, const double* Hm,
                              const double* Arm, int panel_dtype, int grid, hipStream_t st);
 size_t pipe_solve_lds_bytes(const SolveArgs& a, int grid, int stride, int panel_dtype);

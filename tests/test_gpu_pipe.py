@@ -28,14 +28,15 @@ def test_pipe_grid_sizes(rebk, oracle_lib, cfg1, grid_wgs):
     gpu_vs_oracle(rebk, oracle_lib, cfg1, kernel="pipe", grid_wgs=grid_wgs, max_iter=400)
 
 
-def test_pipe_one_workgroup_per_compute_unit(rebk, cfg1):
-    """The kernel holds a workgroup's whole register file: a grid larger than the compute units
-    cannot be co-resident and is refused before launch."""
+def test_pipe_grid_beyond_compute_units(rebk, oracle_lib, cfg1):
+    """512 workgroups, two per compute unit: either all fit at once and the solve matches the
+    oracle (workgroups past the 128 broadcast entries own none), or the launch is refused before
+    it starts because they cannot be co-resident (it depends on the kernel's register count)."""
     S = cfg1
-    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
-    with pytest.raises(rebk.RebkError, match="co-resident"):
-        solver.solve_ex(to_dev(S.b), max_iter=10, kernel="pipe", grid_wgs=512)
-    solver.close()
+    try:
+        gpu_vs_oracle(rebk, oracle_lib, S, kernel="pipe", grid_wgs=512, max_iter=300)
+    except rebk.RebkError as e:
+        assert "co-resident" in str(e)
 
 
 @pytest.mark.parametrize("panel", ["f32", "bf16", "f16"])
