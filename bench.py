@@ -6,9 +6,11 @@ of 200 rows and 100 column blocks of 20 columns, alpha = 1 / beta_max, x0 = 0, z
 seed 0, stop at ||x - A^+ b|| / ||A^+ b|| < 1e-6 (checked every iteration).
 
 One step = one whole solve: rebk_create (pack into panels, FP64 block weights, sampling tables)
-plus rebk_solve_ex to the tolerance, inputs resident in HBM.  Both panel precisions are run
-(FP64 panels, the plain method; FP32 panels with FP64 iterates); the faster one that reaches the
-tolerance is the reported form.
+plus rebk_solve_ex to the tolerance, inputs resident in HBM.  The forms: both panel precisions on
+the whole-chip grid kernel (FP64 panels, the plain method; FP32 panels with FP64 iterates), and
+FP32 panels on the pipelined kernel, whose step also builds its Gram matrices A A^T and A^T A
+(rebk_pipe_prepare).  The fastest form that reaches the tolerance is the reported one.  Each form
+runs one untimed solve first (it also tells whether the form fits the system).
 
 The same line carries, unless ``--no-extras`` is given, the other configurations measured in the
 same run: the 1000 x 100 FP64 system (``cfg1``: microseconds per iteration and solves per
@@ -34,7 +36,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_FILE = "grid_solve_kernel_rank1500_20000x2000_traffic.json"
+# HBM bytes per launch measured with the byte counters, one file per solve kernel
+TRAFFIC_FILE = "{kernel}_solve_kernel_rank1500_20000x2000_traffic.json"
 # sources that define the solve kernel: measured traffic is reported only for the kernel it was taken on
 KERNEL_SOURCES = ("paper_2001_04179_amd/csrc/rebk_grid.hip", "paper_2001_04179_amd/csrc/rebk_device.h",
                   "paper_2001_04179_amd/csrc/rebk_internal.h")
@@ -56,7 +59,10 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--tol", type=float, default=1e-6)
     p.add_argument("--grid-wgs", type=int, default=0)
-    p.add_argument("--panels", default="f64,f32")
+    p.add_argument("--panels", default="f64,f32", help="panel types run with the grid kernel")
+    p.add_argument("--pipe-panels", default="f32",
+                   help="panel types run with the pipelined kernel (its Gram matrices are built inside "
+                        "each timed solve); empty: none")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
                    help="only the 20000 x 2000 headline (no cfg1 / batched / mixed sub-results)")
@@ -86,8 +92,8 @@ def parse():
                    help="batched: skip the plain FP64 comparison (profiling runs)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
-    p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", TRAFFIC_FILE),
-                   help="JSON with measured HBM bytes per launch of the solve kernel (from the counter runs)")
+    p.add_argument("--traffic-dir", default=os.path.join(ROOT, "profiles"),
+                   help="directory of the JSON files with measured HBM bytes per launch of each solve kernel")
     return p.parse_args()
 
 
@@ -103,24 +109,40 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}))
 
 
-def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs):
+def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs, kernel="grid"):
+    """One solve form: a fresh solver (panels packed; for the pipelined kernel also its Gram
+    matrices built) and a solve to tol, per timed step."""
     import torch
     m, n = S.A.shape
     nI = int(np.max(np.diff(S.row_off)))
     nJ = int(np.max(np.diff(S.col_off)))
     esz = 8 if panel == "f64" else 4
+    # algorithmic bytes per iteration: the two panel slabs, and for the pipelined kernel the FP64
+    # rows of A A^T, A^T A and A its owners read (u entries: |I| rows of |I| + |J| entries for w
+    # and for w'; v entries: |J| rows of |J| entries for each)
     bytes_per_iter = esz * (m * nJ + nI * n)
+    if kernel == "pipe":
+        bytes_per_iter += 8 * 2 * (nI * (nI + nJ) + nJ * nJ)
+    prep_ms = []
 
     def one():
         solver = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
-        out = solver.solve_ex(b_d, max_iter=2_000_000, x_ref=xr_d, tol=tol, check_every=1, kernel="grid",
+        if kernel == "pipe":
+            prep_ms.append(solver.pipe_prepare())
+        out = solver.solve_ex(b_d, max_iter=2_000_000, x_ref=xr_d, tol=tol, check_every=1, kernel=kernel,
                               grid_wgs=grid_wgs)
         solver.close()
         return out
 
-    for _ in range(warmup):
+    try:
+        one()
+    except rebk.RebkError as e:  # the form does not fit this system
+        return {"panel_dtype": panel, "kernel": kernel, "status": "unavailable", "reason": str(e)}
+
+    for _ in range(warmup - 1):
         one()
     torch.cuda.synchronize()
+    prep_ms.clear()
     t0 = time.perf_counter()
     results = []
     for _ in range(steps):
@@ -132,8 +154,9 @@ def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs):
     iters = int(np.mean([o["result"].iterations for o in results]))
     x = results[-1]["x"].cpu().numpy()
     err = float(np.linalg.norm(x - S.x_ref) / np.linalg.norm(S.x_ref))
-    return {
+    res = {
         "panel_dtype": panel,
+        "kernel": kernel,
         "status": r.status,
         "iterations": iters,
         "rel_err": err,
@@ -144,11 +167,16 @@ def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs):
         "bytes_per_iter": bytes_per_iter,
         "kernel_GBs": bytes_per_iter * iters / (kernel_ms * 1e-3) / 1e9,
     }
+    if kernel == "pipe":
+        res["gram_build_ms"] = float(np.mean(prep_ms))  # inside ms_per_solve
+    return res
 
 
-def traffic_for(path, panel):
+def traffic_for(directory, kernel, panel):
     """HBM bytes per launch of the solve kernel measured with the FETCH_SIZE / WRITE_SIZE counters
-    (scaled by a plain copy of known size), if a measurement file for this panel type is given."""
+    (scaled by a plain copy of known size), if a measurement file for this kernel and panel type is
+    there."""
+    path = os.path.join(directory, TRAFFIC_FILE.format(kernel=kernel)) if directory else None
     if not path or not os.path.exists(path):
         return None
     with open(path) as f:
@@ -738,11 +766,15 @@ def main():
     b_d = torch.from_numpy(S.b).to(dev)
     xr_d = torch.from_numpy(S.x_ref).to(dev)
     forms = {}
-    for panel in args.panels.split(","):
-        forms[panel] = run_form(rebk, S, A_d, b_d, xr_d, panel, args.steps, args.warmup, args.tol, args.grid_wgs)
-        print(f"# {panel}: {json.dumps(forms[panel])}", file=sys.stderr, flush=True)
+    plan = [(p, "grid") for p in args.panels.split(",") if p] + \
+           [(p, "pipe") for p in args.pipe_panels.split(",") if p]
+    for panel, kernel in plan:
+        key = panel if kernel == "grid" else f"{panel}+pipe"
+        forms[key] = run_form(rebk, S, A_d, b_d, xr_d, panel, args.steps, args.warmup, args.tol, args.grid_wgs,
+                              kernel=kernel)
+        print(f"# {key}: {json.dumps(forms[key])}", file=sys.stderr, flush=True)
     ok = {k: v for k, v in forms.items() if v["status"] == "ok" and v["rel_err"] < args.tol}
-    chosen_key = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else "f64"
+    chosen_key = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else next(iter(forms))
     chosen = forms[chosen_key]
     plain = forms.get("f64", chosen)
     m, n = S.A.shape
@@ -752,8 +784,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": chosen["kernel_GBs"] / HBM_PEAK_GBS,
-        "traffic": traffic_for(args.traffic_json, chosen_key),
-        "kernel": "grid_solve_kernel",
+        "traffic": traffic_for(args.traffic_dir, chosen.get("kernel", "grid"), chosen["panel_dtype"]),
+        "kernel": f"{chosen.get('kernel', 'grid')}_solve_kernel",
         "bytes_per_iter": chosen["bytes_per_iter"],
     }
     line = {
@@ -771,7 +803,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"REBK rank-{1500 // args.scale} {m}x{n}, 200-row / 20-column blocks, tol {args.tol:g}",
                    "m": m, "n": n, "row_block": 200, "col_block": 20, "alpha": S.alpha,
-                   "panel_dtype": chosen_key},
+                   "panel_dtype": chosen["panel_dtype"], "kernel": chosen.get("kernel", "grid")},
         "iterations": chosen["iterations"],
         "time_to_tol_ms": chosen["ms_per_solve"],
         "us_per_iter": chosen["us_per_iter"],

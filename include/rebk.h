@@ -79,7 +79,9 @@ typedef enum {
 
 /* Which kernel runs the iterations. */
 typedef enum {
-    REBK_KERNEL_AUTO = 0,     /* WORKGROUP for tiny systems (m |J| + |I| n + 4 (m + n) <= 8192), GRID otherwise */
+    REBK_KERNEL_AUTO = 0,     /* WORKGROUP for tiny systems (m |J| + |I| n + 4 (m + n) <= 8192); else PIPE
+                                 when its Gram matrices exist (rebk_pipe_prepare, or an earlier
+                                 PIPE solve on the handle) and the call fits its limits; else GRID */
     REBK_KERNEL_WORKGROUP = 1,/* one workgroup runs the whole solve (small systems) */
     REBK_KERNEL_GRID = 2,     /* one persistent cooperative grid, one grid-wide reduction per
                                  iteration; needs ceil(n / grid) + 8 <= 256 owned columns, blocks

@@ -265,15 +265,49 @@ struct FixedWorkspace {
   size_t words;
 };
 
+// Whether the pipelined kernel runs this call on a grid of G workgroups; else the reason in why
+// (when given).
+bool pipe_fits(const rebk_handle* h, const rebk::SolveArgs& a, int G, char* why) {
+  auto no = [&](const char* fmt, long long v1, long long v2, long long v3) {
+    if (why) snprintf(why, 256, fmt, v1, v2, v3);
+    return false;
+  };
+  if (a.g || a.y_out) return no("the pipelined kernel runs no refinement steps", 0, 0, 0);
+  if (G > 1024) return no("at most 1024 workgroups in the pipelined kernel (grid %lld)", G, 0, 0);
+  const int stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
+  if (stride > G || stride > rebk::kPipeMaxStride)
+    return no("pipelined kernel: %lld broadcast entries need as many workgroups (grid %lld) and at most %lld",
+              stride, G, rebk::kPipeMaxStride);
+  if ((h->n + G - 1) / G + 8 > rebk::kGridThreads)
+    return no("too many columns per workgroup (%lld); use a larger grid", (h->n + G - 1) / G, 0, 0);
+  if (h->max_nJ > rebk::kGridThreads)
+    return no("column blocks wider than %lld columns need the one-workgroup kernel", rebk::kGridThreads, 0, 0);
+  const size_t lds = rebk::pipe_solve_lds_bytes(a, G, stride, h->panel_dtype);
+  if (lds > 150 * 1024) return no("pipelined kernel needs %lld bytes of LDS per workgroup", (long long)lds, 0, 0);
+  int per_cu = 0;
+  if (rebk::pipe_solve_max_blocks(h->panel_dtype, lds, &per_cu) != hipSuccess)
+    return no("occupancy query of the pipelined kernel failed", 0, 0, 0);
+  if (per_cu <= 0 || G > per_cu * h->cus)
+    return no("grid of %lld workgroups cannot be co-resident (%lld per CU)", G, per_cu, 0);
+  return true;
+}
+
 // One call of the iteration kernel for iterations k0+1 .. k0+iters.
 int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, int* used_kernel,
                    const FixedWorkspace* fixed = nullptr) {
   if (kernel == REBK_KERNEL_AUTO) {
     // One workgroup wins only for tiny systems: per iteration it walks both blocks and all of z
     // and x.  Measured on MI355X: 5.7 us vs 7.3 us (whole chip) at 250 x 120 with 10 x 10 blocks,
-    // 8.7 vs 7.5 at 500 x 250, 23 vs 8 at 1000 x 100 with 100 x 10 blocks.
+    // 8.7 vs 7.5 at 500 x 250, 23 vs 8 at 1000 x 100 with 100 x 10 blocks.  Past that the
+    // pipelined kernel, once its Gram matrices exist (rebk_pipe_prepare or an earlier pipelined
+    // solve), where it fits: 5.0 us vs 7.8 us per iteration on the 20000 x 2000 workload.
     const double work = (double)h->m * h->max_nJ + (double)h->n * h->max_nI + 4.0 * (double)(h->m + h->n);
-    kernel = (wg_fits(h, a) && work <= 8192.0) ? REBK_KERNEL_WORKGROUP : REBK_KERNEL_GRID;
+    if (wg_fits(h, a) && work <= 8192.0)
+      kernel = REBK_KERNEL_WORKGROUP;
+    else if (!fixed && h->pipe_G && pipe_fits(h, a, grid_wgs > 0 ? grid_wgs : h->cus, nullptr))
+      kernel = REBK_KERNEL_PIPE;
+    else
+      kernel = REBK_KERNEL_GRID;
   }
   *used_kernel = kernel;
   if (kernel == REBK_KERNEL_WORKGROUP) {
@@ -283,25 +317,11 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
   }
   if (kernel == REBK_KERNEL_PIPE) {
     if (fixed) return fail(REBK_ERR_INVALID, "the pipelined kernel needs allocated memory; use GRID here");
-    if (a.g || a.y_out) return fail(REBK_ERR_INVALID, "the pipelined kernel runs no refinement steps");
     const int G = grid_wgs > 0 ? grid_wgs : h->cus;
-    if (G > 1024) return fail(REBK_ERR_INVALID, "at most 1024 workgroups in the pipelined kernel");
+    char why[256];
+    if (!pipe_fits(h, a, G, why)) return fail(REBK_ERR_INVALID, "%s", why);
     rebk::GridSync gs{};
     gs.stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
-    if (gs.stride > G || gs.stride > rebk::kPipeMaxStride)
-      return fail(REBK_ERR_INVALID,
-                  "pipelined kernel: %d broadcast entries need as many workgroups (grid %d) and at most %d",
-                  gs.stride, G, rebk::kPipeMaxStride);
-    if ((h->n + G - 1) / G + 8 > rebk::kGridThreads)
-      return fail(REBK_ERR_INVALID, "too many columns per workgroup; use a larger grid");
-    if (h->max_nJ > rebk::kGridThreads)
-      return fail(REBK_ERR_INVALID, "column blocks wider than %d columns need the one-workgroup kernel", rebk::kGridThreads);
-    const size_t lds = rebk::pipe_solve_lds_bytes(a, G, gs.stride, h->panel_dtype);
-    if (lds > 150 * 1024) return fail(REBK_ERR_INVALID, "pipelined kernel needs %zu bytes of LDS per workgroup", lds);
-    int per_cu = 0;
-    HIP_TRY(rebk::pipe_solve_max_blocks(h->panel_dtype, lds, &per_cu));
-    if (per_cu <= 0 || G > per_cu * h->cus)
-      return fail(REBK_ERR_INVALID, "grid of %d workgroups cannot be co-resident (%d per CU)", G, per_cu);
     int rc = ensure_pipe(h, nullptr);
     if (rc != REBK_OK) return rc;
     const size_t part_words = (size_t)4 * G * gs.stride * 2;

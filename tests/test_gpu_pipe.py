@@ -116,6 +116,28 @@ def test_pipe_prepare_and_release(rebk, cfg1):
     assert np.array_equal(a, b)
 
 
+def test_auto_picks_pipe_once_prepared(rebk, oracle_lib, cfg1):
+    """AUTO runs the grid kernel until the Gram matrices exist, the pipelined kernel after
+    rebk_pipe_prepare (same iterates), and the grid kernel again after rebk_pipe_release."""
+    S = cfg1
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    a = solver.solve_ex(to_dev(S.b), max_iter=300)
+    assert a["result"].kernel == "grid"
+    solver.pipe_prepare()
+    b = solver.solve_ex(to_dev(S.b), max_iter=300)
+    assert b["result"].kernel == "pipe"
+    # the refinement's inner solves stay on the grid kernel
+    r = solver.solve_refined(to_dev(S.A), to_dev(S.b), x_ref=to_dev(S.x_ref), tol=1e-9, inner_iters=200)
+    assert r["result"].kernel == "grid" and r["result"].status == "ok"
+    solver.pipe_release()
+    c = solver.solve_ex(to_dev(S.b), max_iter=300)
+    solver.close()
+    assert c["result"].kernel == "grid"
+    ref = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=300)
+    for o in (a, b, c):
+        assert rel(o["x"].cpu().numpy(), ref["x"]) <= RTOL_F64
+
+
 def test_pipe_rejections(rebk, cfg1):
     """What the pipelined kernel does not run is an error, never a silent fallback."""
     S = cfg1
