@@ -273,6 +273,7 @@ bool pipe_fits(const rebk_handle* h, const rebk::SolveArgs& a, int G, char* why)
     return false;
   };
   if (a.g || a.y_out) return no("the pipelined kernel runs no refinement steps", 0, 0, 0);
+  if (a.max_iter > INT32_MAX - 64) return no("the pipelined kernel runs at most %lld iterations per call", INT32_MAX - 64, 0, 0);
   if (G > 1024) return no("at most 1024 workgroups in the pipelined kernel (grid %lld)", G, 0, 0);
   const int stride = ((h->max_nJ + h->max_nI + 1 + 31) / 32) * 32;
   if (stride > G || stride > rebk::kPipeMaxStride)

@@ -806,15 +806,34 @@ __device__ __forceinline__ double dot_strided(const TP* a, int sa, const double*
   return (s0 + s1) + (s2 + s3);
 }
 
+// One block draw as the pipelined kernel keeps it in LDS (one 32-byte record).
+struct PipeDraw {
+  int nJ, nI;   // block sizes
+  int c0, r0;   // first column of J, first row of I
+  double cc, cr;  // alpha / ||A_{:,J}||_F^2, alpha / ||A_{I,:}||_F^2
+};
+// The record read by every lane of the wave at the same LDS address, made wave-uniform.
+__device__ __forceinline__ PipeDraw uniform_draw(const PipeDraw& s) {
+  PipeDraw d = s;
+  d.nJ = __builtin_amdgcn_readfirstlane(d.nJ);
+  d.nI = __builtin_amdgcn_readfirstlane(d.nI);
+  d.c0 = __builtin_amdgcn_readfirstlane(d.c0);
+  d.r0 = __builtin_amdgcn_readfirstlane(d.r0);
+  d.cc = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(d.cc)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(d.cc)));
+  d.cr = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(d.cr)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(d.cr)));
+  return d;
+}
+
 template <typename TP>
 __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, GridSync gs,
                                                                   const double* __restrict__ Gm,
                                                                   const double* __restrict__ Hm,
                                                                   const double* __restrict__ Arm) {
   extern __shared__ double lds[];
-  __shared__ int s_j[kRing], s_i[kRing], s_nJ[kRing], s_nI[kRing];
-  __shared__ int64_t s_c0[kRing], s_r0[kRing];
-  __shared__ double s_cc[kRing], s_cr[kRing];
+  __shared__ int s_j[kRing], s_i[kRing];
+  __shared__ PipeDraw s_dr[kRing];  // draw of iteration q in slot (q - 1) & (kRing - 1); zero past K
   __shared__ int s_ok;
   // handshakes between the waves (values are round or iteration numbers, nondecreasing)
   __shared__ int s_zflag[2];  // z^t of the owned rows, half h, is in LDS for t <= s_zflag[h]
@@ -848,7 +867,9 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   const TP* __restrict__ Arow = (const TP*)a.Arow;
   const TP* __restrict__ Acol = (const TP*)a.Acol;
   const int64_t K = a.max_iter;
+  const int K32 = (int)K;  // (below 2^31; rounds and iterations are 32-bit here)
   const int64_t ce = a.check_every > 0 ? a.check_every : 1;
+  const int ce32 = (int)(ce < K ? ce : K);
   const bool checking = a.x_ref != nullptr && a.tol > 0.0;
   const bool final_err = a.x_ref != nullptr;
   const int err_slot = MJ + MI;
@@ -866,49 +887,56 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   }
   for (int q = tid; q < 7 * E + 2; q += T) bv[q] = 0.0;
 
-  auto slot = [&](int64_t q) -> int { return (int)((q - 1) & (kRing - 1)); };
-  auto refill = [&](int64_t first, int t0) {  // draws first .. first + 63 (lanes of the wave at t0)
+    auto refill = [&](int64_t first, int t0) {  // draws first .. first + 63 (lanes of the wave at t0)
     const int l = tid - t0;
     if (l >= 0 && l < 64) {
       const int64_t q = first + l;
+      const int sl = (int)((q - 1) & (kRing - 1));
+      PipeDraw d{0, 0, 0, 0, 0.0, 0.0};
       if (q <= K) {
         int jj, ii;
         draw_pair(a, a.k0 + q, jj, ii);
-        const int sl = (int)((q - 1) & (kRing - 1));
         s_j[sl] = jj;
         s_i[sl] = ii;
-        s_c0[sl] = a.col_off[jj];
-        s_nJ[sl] = (int)(a.col_off[jj + 1] - a.col_off[jj]);
-        s_r0[sl] = a.row_off[ii];
-        s_nI[sl] = (int)(a.row_off[ii + 1] - a.row_off[ii]);
-        s_cc[sl] = a.coef_col[jj];
-        s_cr[sl] = a.coef_row[ii];
+        d.c0 = (int)a.col_off[jj];
+        d.nJ = (int)(a.col_off[jj + 1] - a.col_off[jj]);
+        d.r0 = (int)a.row_off[ii];
+        d.nI = (int)(a.row_off[ii + 1] - a.row_off[ii]);
+        d.cc = a.coef_col[jj];
+        d.cr = a.coef_row[ii];
       }
+      s_dr[sl] = d;
     }
   };
-  // sizes and coefficients of iteration t (0 outside 1..K)
-  auto nJ_of = [&](int64_t t) -> int { return (t >= 1 && t <= K) ? s_nJ[slot(t)] : 0; };
-  auto nI_of = [&](int64_t t) -> int { return (t >= 1 && t <= K) ? s_nI[slot(t)] : 0; };
-  auto cc_of = [&](int64_t t) -> double { return (t >= 1 && t <= K) ? s_cc[slot(t)] : 0.0; };
-  auto cr_of = [&](int64_t t) -> double { return (t >= 1 && t <= K) ? s_cr[slot(t)] : 0.0; };
-  auto colslab = [&](int64_t t) -> TP* { return slabC + (size_t)(t % kPipeSlabs) * L.slabC; };
-  auto rowslab = [&](int64_t t) -> TP* { return slabR + (size_t)(t % kPipeSlabs) * L.slabR; };
+  // draw of iteration t as wave-uniform values (all zero outside 1..K: the records past K are)
+  auto drw = [&](int t) -> PipeDraw {
+    PipeDraw d{0, 0, 0, 0, 0.0, 0.0};
+    if (t >= 1) d = uniform_draw(s_dr[(t - 1) & (kRing - 1)]);
+    return d;
+  };
+  auto nJ_of = [&](int t) -> int { return drw(t).nJ; };
+  auto nI_of = [&](int t) -> int { return drw(t).nI; };
+  auto cc_of = [&](int t) -> double { return drw(t).cc; };
+  auto cr_of = [&](int t) -> double { return drw(t).cr; };
+  auto colslab = [&](int t) -> TP* { return slabC + (size_t)(t % kPipeSlabs) * L.slabC; };
+  auto rowslab = [&](int t) -> TP* { return slabR + (size_t)(t % kPipeSlabs) * L.slabR; };
   // round t carries the error of x^{t-3} when a check is due (and the last error, of x^K)
-  auto err_round = [&](int64_t t) -> bool {
-    const int64_t k = t - 3;
-    return k >= 1 && k <= K && ((checking && k % ce == 0) || (final_err && k == K));
+  auto err_round = [&](int t) -> bool {
+    const int k = t - 3;
+    return k >= 1 && k <= K32 && ((checking && k % ce32 == 0) || (final_err && k == K32));
   };
   // entries of round t (polled in the broadcast and gathered by owners)
-  auto need = [&](int64_t t, int e) -> bool {  // (false for e < 0: a workgroup that owns no entry)
-    return (e >= 0 && e < MJ && e < nJ_of(t + 1)) || (e >= MJ && e < MJ + MI && e - MJ < nI_of(t)) ||
-           (e == err_slot && err_round(t));
+  // entry e of round t is broadcast: nJn = |J_{t+1}|, nIt = |I_t|, er = err_round(t)
+  auto need_d = [&](int e, int nJn, int nIt, bool er) -> bool {  // (false for e < 0: no entry owned)
+    return (e >= 0 && e < MJ && e < nJn) || (e >= MJ && e < MJ + MI && e - MJ < nIt) || (e == err_slot && er);
   };
+  auto need = [&](int t, int e) -> bool { return need_d(e, nJ_of(t + 1), nI_of(t), err_round(t)); };
 
   // ---- copies into LDS
   // Column slab of J_t: nJ runs of the owned rows, each c16 16-byte chunks (the column panels are
   // padded to 16 entries, so a rounded-up run stays inside its column); run c at c * nrs.
-  auto colsrc = [&](int64_t t) -> const char* { return (const char*)(Acol + a.ldc * s_c0[slot(t)] + r0); };
-  auto col_direct = [&](int64_t t, int from, int l0, int nl) {  // chunks from `from` on
+  auto colsrc = [&](int t) -> const char* { return (const char*)(Acol + a.ldc * drw(t).c0 + r0); };
+  auto col_direct = [&](int t, int from, int l0, int nl) {  // chunks from `from` on
     const int nJ = nr > 0 ? nJ_of(t) : 0;
     if (nJ == 0) return;
     const char* src = colsrc(t);
@@ -920,13 +948,16 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   };
   // Row slab of I_t: one run of nc x nI entries, copied in dwords when it starts on a dword (2-byte
   // panels at an odd offset and a 2-byte tail go entry by entry).
-  auto rowsrc = [&](int64_t t) -> const TP* { return Arow + n * s_r0[slot(t)] + cA * nI_of(t); };
-  auto row_dwords = [&](int64_t t) -> int {
+  auto rowsrc = [&](int t) -> const TP* {
+    const PipeDraw d = drw(t);
+    return Arow + n * d.r0 + cA * d.nI;
+  };
+  auto row_dwords = [&](int t) -> int {
     const int nI = nI_of(t);
     if (nI == 0 || nc == 0 || ((uintptr_t)rowsrc(t) & 3) != 0) return 0;
     return nc * nI * esz / 4;
   };
-  auto row_direct = [&](int64_t t, int from_dw, int l0, int nl) {  // dwords from `from_dw` on, then entries
+  auto row_direct = [&](int t, int from_dw, int l0, int nl) {  // dwords from `from_dw` on, then entries
     const int nI = nI_of(t);
     if (nI == 0 || nc == 0) return;
     const TP* src = rowsrc(t);
@@ -967,28 +998,29 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
       src = S.s3 + d, dst = S.d3 + d;
     }
   };
-  auto segs_w = [&](Seg& S, int64_t t) {
-    if (!need(t, e_own)) return;
+  // (draws of iterations t - 2 .. t + 1 read once: d[k] is the draw of t - 2 + k)
+  auto segs_w = [&](Seg& S, int t, const PipeDraw* d) {
+    if (!need_d(e_own, d[3].nJ, d[2].nI, err_round(t))) return;
     double* dst = wr + (size_t)(t & 1) * E;
     if (v_owner) {
-      const int64_t C = s_c0[slot(t + 1)] + e_own;
-      if (nJ_of(t) > 0) seg_add(S, Hm + C * n + s_c0[slot(t)], dst, nJ_of(t));
+      const int64_t C = (int64_t)d[3].c0 + e_own;
+      seg_add(S, Hm + C * n + d[2].c0, dst, d[2].nJ);
     } else if (u_owner) {
-      const int64_t R = s_r0[slot(t)] + (e_own - MJ);
-      if (nJ_of(t) > 0) seg_add(S, Arm + R * n + s_c0[slot(t)], dst, nJ_of(t));
-      if (nI_of(t - 1) > 0) seg_add(S, Gm + R * m + s_r0[slot(t - 1)], dst + MJ, nI_of(t - 1));
+      const int64_t R = (int64_t)d[2].r0 + (e_own - MJ);
+      seg_add(S, Arm + R * n + d[2].c0, dst, d[2].nJ);
+      seg_add(S, Gm + R * m + d[1].r0, dst + MJ, d[1].nI);
     }
   };
-  auto segs_wp = [&](Seg& S, int64_t t) {
-    if (!need(t, e_own)) return;
+  auto segs_wp = [&](Seg& S, int t, const PipeDraw* d) {
+    if (!need_d(e_own, d[3].nJ, d[2].nI, err_round(t))) return;
     double* dst = wpr + (size_t)(t & 1) * E;
     if (v_owner) {
-      const int64_t C = s_c0[slot(t + 1)] + e_own;
-      if (nJ_of(t - 1) > 0) seg_add(S, Hm + C * n + s_c0[slot(t - 1)], dst, nJ_of(t - 1));
+      const int64_t C = (int64_t)d[3].c0 + e_own;
+      seg_add(S, Hm + C * n + d[1].c0, dst, d[1].nJ);
     } else if (u_owner) {
-      const int64_t R = s_r0[slot(t)] + (e_own - MJ);
-      if (nJ_of(t - 1) > 0) seg_add(S, Arm + R * n + s_c0[slot(t - 1)], dst, nJ_of(t - 1));
-      if (nI_of(t - 2) > 0) seg_add(S, Gm + R * m + s_r0[slot(t - 2)], dst + MJ, nI_of(t - 2));
+      const int64_t R = (int64_t)d[2].r0 + (e_own - MJ);
+      seg_add(S, Arm + R * n + d[1].c0, dst, d[1].nJ);
+      seg_add(S, Gm + R * m + d[0].r0, dst + MJ, d[0].nI);
     }
   };
   auto seg_direct = [&](const Seg& S, int from, int l0, int nl) {  // flattened entries from `from` on
@@ -1021,7 +1053,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   const int p2 = lane & 1;
   const bool first = p2 == 0;
   // Gather: the sum over workgroups of entry e of the partial vectors of round t (one wave).
-  auto gather = [&](int64_t t, int e) -> double {
+  auto gather = [&](int t, int e) -> double {
     const unsigned long long* Pp = gs.part + (size_t)(t & (kPipeParts - 1)) * G * V2 + (size_t)e * 2;
     const unsigned ep = (unsigned)(t + 1);
     double acc = 0.0;
@@ -1074,7 +1106,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   // ---- partial sums of round t from z (owned rows) and x (owned columns):
   //   v entries A_{J_{t+1}}^T z over owned rows (one wave), u entries A_{I_t} x - b + z (one wave),
   //   and ||x - x_ref||^2 when due (the u wave)
-  auto part_v = [&](int64_t t, const double* zc, int c_lo, int c_hi) {  // columns [c_lo, c_hi), whole wave
+  auto part_v = [&](int t, const double* zc, int c_lo, int c_hi) {  // columns [c_lo, c_hi), whole wave
     unsigned long long* P = gs.part + ((size_t)(t & (kPipeParts - 1)) * G + w) * V2;
     const unsigned ep = (unsigned)(t + 1);
     const int nJn = c_hi < nJ_of(t + 1) ? c_hi : nJ_of(t + 1);
@@ -1090,13 +1122,13 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     }
   };
   // rows [l_lo, l_hi) of I_t (whole wave); with_err: also ||x - x_ref||^2 when due
-  auto part_u = [&](int64_t t, const double* xc, const double* zc, int zready, int l_lo, int l_hi, bool with_err) {
+  auto part_u = [&](int t, const double* xc, const double* zc, int zready, int l_lo, int l_hi, bool with_err) {
     unsigned long long* P = gs.part + ((size_t)(t & (kPipeParts - 1)) * G + w) * V2;
     const unsigned ep = (unsigned)(t + 1);
     const int nIt = nI_of(t), lend = l_hi < nIt ? l_hi : nIt;
     if (lend > l_lo) {
       const TP* Sr = rowslab(t);
-      const int64_t rI = s_r0[slot(t)];
+      const int64_t rI = drw(t).r0;
       bool waited = false;
       for (int l0 = l_lo; l0 < lend; l0 += 64) {
         const int l = l0 + lane;
@@ -1128,7 +1160,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     }
   };
   // z^t = z^{t-1} - c'_t A_{J_t} v^t on owned rows (one wave), v^t = B^{t-1}[0, nJ)
-  auto zstep = [&](int64_t t, const double* vB, int p_lo, int p_hi) {  // owned rows [p_lo, p_hi)
+  auto zstep = [&](int t, const double* vB, int p_lo, int p_hi) {  // owned rows [p_lo, p_hi)
     const int nJ = nJ_of(t);
     const TP* Sl = colslab(t);
     const double coef = cc_of(t);
@@ -1137,7 +1169,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     for (int p = p_lo + lane; p < p_hi; p += 64) zn[p] = zo[p] - coef * dot_strided(Sl + p, nrs, vB, 1, nJ);
   };
   // x^t = x^{t-1} - c_t A_{I_t}^T u^t on owned columns (one wave), u^t = B^t[MJ, MJ + nI)
-  auto xstep = [&](int64_t t, const double* uB, int c_lo, int c_hi) {  // owned columns [c_lo, c_hi)
+  auto xstep = [&](int t, const double* uB, int c_lo, int c_hi) {  // owned columns [c_lo, c_hi)
     if (c_hi <= c_lo) return;
     const int nI = nI_of(t);
     const TP* Sl = rowslab(t);
@@ -1175,7 +1207,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   // Copies for later rounds, one wave each (all loads issued before any is written to LDS; the
   // waves have nothing else on their path until the round's end): the column slab of J_t in
   // 16-byte chunks, the row slab of I_t in dwords, the raw rows of w_t and w'_{t+1} in doubles.
-  auto copy_col = [&](int64_t t) {
+  auto copy_col = [&](int t) {
     const int ncol = nr > 0 ? nJ_of(t) * c16 : 0;
     if (ncol == 0) return;
     const char* src = colsrc(t);
@@ -1204,7 +1236,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
       if (at[k] >= 0) dst[at[k]] = v[k];
     if (ncol > 64 * (kPipeStage / 4)) col_direct(t, 64 * (kPipeStage / 4), lane, 64);
   };
-  auto copy_row = [&](int64_t t, auto&& between) {  // `between` runs while the loads are in flight
+  auto copy_row = [&](int t, auto&& between) {  // `between` runs while the loads are in flight
     const int nrow = row_dwords(t);
     uint32_t v[kPipeStage];
     if (nrow > 0) {
@@ -1222,11 +1254,14 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     }
     row_direct(t, 64 * kPipeStage, lane, 64);
   };
-  auto copy_w = [&](int64_t t) {  // w_t and w'_{t+1}
+  auto copy_w = [&](int t) {  // w_t and w'_{t+1}
+    PipeDraw d[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) d[q] = drw(t - 2 + q);  // t - 2 .. t + 2
     Seg S;
     seg_clear(S);
-    segs_w(S, t);
-    segs_wp(S, t + 1);
+    segs_w(S, t, d);
+    segs_wp(S, t + 1, d + 1);
     const int tot = S.l0 + S.l1 + S.l2 + S.l3;
     double v[kPipeStage / 2];
     int at[kPipeStage / 2];
@@ -1263,9 +1298,12 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     for (int64_t t = 1; t <= 3; ++t) row_direct(t, 0, tid, T);
     Seg P;  // at most two segments per vector
     for (int v = 0; v < 4; ++v) {
+      const int t = v < 2 ? 1 + v : v;
+      PipeDraw d[4];
+      for (int q = 0; q < 4; ++q) d[q] = drw(t - 2 + q);
       seg_clear(P);
-      if (v < 2) segs_w(P, 1 + v);
-      else segs_wp(P, v);
+      if (v < 2) segs_w(P, t, d);
+      else segs_wp(P, t, d);
       seg_direct(P, 0, tid, T);
     }
   }
@@ -1303,10 +1341,10 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   bool alive = s_ok != 0;
   // After the workgroup barrier of round r (B^r in LDS): the stop rule on the error B^r carries,
   // the same decision in every wave.  Returns true when the solve ends here (outputs written).
-  auto round_end = [&](int64_t r) -> bool {
+  auto round_end = [&](int r) -> bool {
     if (tid == 0 && w == 0 && a.trace_j && r >= 1 && r <= K) {
-      a.trace_j[r - 1] = s_j[slot(r)];
-      a.trace_i[r - 1] = s_i[slot(r)];
+      a.trace_j[r - 1] = s_j[(r - 1) & (kRing - 1)];
+      a.trace_i[r - 1] = s_i[(r - 1) & (kRing - 1)];
     }
     if (!err_round(r)) return false;
     const double e2 = bv[(size_t)(r % 3) * E + err_slot];  // the error of x^{r-3}
@@ -1333,15 +1371,19 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     double W1[8], W2[8];
     load_w(W1, wr + (size_t)(1 & 1) * E, need(1, e_own), 1, 0);
     load_w(W2, wpr + (size_t)(2 & 1) * E, need(2, e_own), 1, 0);
-    for (int64_t r = 0; alive; ++r) {
+    for (int r = 0; alive; ++r) {
       const unsigned epB = (unsigned)(r + 1);
       const unsigned long long* Sg =
           gs.gsum + (size_t)(epB % kGridSumRing) * kCopies * V2 + (size_t)(w % kCopies) * V2;
       unsigned needm = 0;  // entries of B^r this lane reads, one bit per register
+      {
+        const int nJn = nJ_of(r + 1), nIr = nI_of(r);
+        const bool er = err_round(r);
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int q = k * 32 + (lane >> 1);
-        if (q < E && need(r, q)) needm |= 1u << k;
+        for (int k = 0; k < 8; ++k) {
+          const int q = k * 32 + (lane >> 1);
+          if (q < E && need_d(q, nJn, nIr, er)) needm |= 1u << k;
+        }
       }
       const bool any = __any(needm != 0);
       const bool publish = e_own >= 0 && need(r + 1, e_own);
@@ -1413,7 +1455,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     }
   } else {
     // ---- waves 1..3: round r of the helpers, after B^r is in LDS
-    for (int64_t r = 0; alive; ++r) {
+    for (int r = 0; alive; ++r) {
       if (!ok) s_ok = 0;
       lds_barrier();
       if (s_ok == 0) {
