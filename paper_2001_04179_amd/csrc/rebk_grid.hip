@@ -873,6 +873,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   const bool checking = a.x_ref != nullptr && a.tol > 0.0;
   const bool final_err = a.x_ref != nullptr;
   const int err_slot = MJ + MI;
+  const int EU = MJ + MI + 1;  // entries in use (v, u and the error); their owners publish every round
   const size_t V2 = (size_t)E * 2;
   const int e_own = w < E ? w : -1;  // the entry this workgroup owns (E <= G)
   const bool v_owner = e_own >= 0 && e_own < MJ, u_owner = e_own >= MJ && e_own < MJ + MI;
@@ -966,77 +967,44 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     for (int d = from_dw + l0; d < ndw; d += nl) ((uint32_t*)dst)[d] = ((gdword*)src)[d];
     for (int e = ndw * 4 / esz + l0; e < nc * nI; e += nl) dst[e] = src[e];
   };
-  // Raw rows of w_t (wr) and w'_t (wpr) for this workgroup's entry: up to two segments of doubles
-  // each (v owner: a row of H; u owner: a row of A, then a row of G at offset MJ).
-  struct Seg {
-    const double *s0, *s1, *s2, *s3;
-    double *d0, *d1, *d2, *d3;
-    int l0, l1, l2, l3;  // lengths (0: unused)
+  // Coefficient vectors of this workgroup's entry, scaled, in the layout of the broadcast (E
+  // doubles, zero outside the entries they multiply).  W_t multiplies B^{t-1} (the correction
+  // -w_t . B^{t-1}): its v part is c'_t times the row over J_t, its u part c_{t-1} times the row of
+  // G over I_{t-1}.  W'_t multiplies B^{t-2}: the same rows over J_{t-1} and I_{t-2}, scaled by
+  // c'_{t-1} and c_{t-2}.  The rows: a v owner's row c0(J_{t+1}) + e of H; a u owner's row
+  // R = r0(I_t) + e - MJ of A (v part) and of G (u part).  Zero when entry e of round t is not
+  // broadcast (and for workgroups that own no v or u entry).
+  struct WSrc {
+    const double *bv, *bu;  // the rows at the first entry of each part
+    int nv, nu;             // lengths of the parts (0: none)
+    double sv, su;          // scale factors
   };
-  auto seg_add = [&](Seg& S, const double* src, double* dst, int len) {  // at most four per Seg
-    if (len <= 0) return;
-    if (S.l0 == 0) {
-      S.s0 = src, S.d0 = dst, S.l0 = len;
-    } else if (S.l1 == 0) {
-      S.s1 = src, S.d1 = dst, S.l1 = len;
-    } else if (S.l2 == 0) {
-      S.s2 = src, S.d2 = dst, S.l2 = len;
-    } else {
-      S.s3 = src, S.d3 = dst, S.l3 = len;
-    }
-  };
-  // flattened entry d of the segments: source and destination (d below the total)
-  auto seg_at = [&](const Seg& S, int d, const double*& src, double*& dst) {
-    if (d < S.l0) {
-      src = S.s0 + d, dst = S.d0 + d;
-    } else if ((d -= S.l0) < S.l1) {
-      src = S.s1 + d, dst = S.d1 + d;
-    } else if ((d -= S.l1) < S.l2) {
-      src = S.s2 + d, dst = S.d2 + d;
-    } else {
-      d -= S.l2;
-      src = S.s3 + d, dst = S.d3 + d;
-    }
-  };
-  // (draws of iterations t - 2 .. t + 1 read once: d[k] is the draw of t - 2 + k)
-  auto segs_w = [&](Seg& S, int t, const PipeDraw* d) {
-    if (!need_d(e_own, d[3].nJ, d[2].nI, err_round(t))) return;
-    double* dst = wr + (size_t)(t & 1) * E;
+  auto wsrc = [&](int t, bool prime) -> WSrc {
+    WSrc q{nullptr, nullptr, 0, 0, 0.0, 0.0};
+    if (!v_owner && !u_owner) return q;
+    const PipeDraw dn = drw(t + 1), dt = drw(t);
+    if (!need_d(e_own, dn.nJ, dt.nI, err_round(t))) return q;
+    const PipeDraw dv = prime ? drw(t - 1) : dt, du = drw(prime ? t - 2 : t - 1);
+    q.nv = dv.nJ;
+    q.sv = dv.cc;
     if (v_owner) {
-      const int64_t C = (int64_t)d[3].c0 + e_own;
-      seg_add(S, Hm + C * n + d[2].c0, dst, d[2].nJ);
-    } else if (u_owner) {
-      const int64_t R = (int64_t)d[2].r0 + (e_own - MJ);
-      seg_add(S, Arm + R * n + d[2].c0, dst, d[2].nJ);
-      seg_add(S, Gm + R * m + d[1].r0, dst + MJ, d[1].nI);
+      q.bv = Hm + ((int64_t)dn.c0 + e_own) * n + dv.c0;
+    } else {
+      const int64_t R = (int64_t)dt.r0 + (e_own - MJ);
+      q.bv = Arm + R * n + dv.c0;
+      q.bu = Gm + R * m + du.r0;
+      q.nu = du.nI;
+      q.su = du.cr;
     }
+    return q;
   };
-  auto segs_wp = [&](Seg& S, int t, const PipeDraw* d) {
-    if (!need_d(e_own, d[3].nJ, d[2].nI, err_round(t))) return;
-    double* dst = wpr + (size_t)(t & 1) * E;
-    if (v_owner) {
-      const int64_t C = (int64_t)d[3].c0 + e_own;
-      seg_add(S, Hm + C * n + d[1].c0, dst, d[1].nJ);
-    } else if (u_owner) {
-      const int64_t R = (int64_t)d[2].r0 + (e_own - MJ);
-      seg_add(S, Arm + R * n + d[1].c0, dst, d[1].nJ);
-      seg_add(S, Gm + R * m + d[0].r0, dst + MJ, d[0].nI);
-    }
+  // entry q of the vector (q < E): its source, or null for a zero
+  auto wsrc_at = [&](const WSrc& v, int q) -> const double* {
+    return q < v.nv ? v.bv + q : ((q >= MJ && q - MJ < v.nu) ? v.bu + (q - MJ) : nullptr);
   };
-  auto seg_direct = [&](const Seg& S, int from, int l0, int nl) {  // flattened entries from `from` on
-    const int tot = S.l0 + S.l1 + S.l2 + S.l3;
-    for (int d = from + l0; d < tot; d += nl) {
-      const double* src;
-      double* dst;
-      seg_at(S, d, src, dst);
-      *dst = *(gdouble*)src;
-    }
-  };
-  auto seg_clear = [&](Seg& S) {
-    S.s0 = S.s1 = S.s2 = S.s3 = nullptr;
-    S.d0 = S.d1 = S.d2 = S.d3 = nullptr;
-    S.l0 = S.l1 = S.l2 = S.l3 = 0;
-  };
+  auto wscale = [&](const WSrc& v, int q) -> double { return q < MJ ? v.sv : v.su; };
+  auto wr_of = [&](int t) -> double* { return wr + (size_t)(t & 1) * E; };    // W_t
+  auto wpr_of = [&](int t) -> double* { return wpr + (size_t)(t & 1) * E; };  // W'_t
 
   unsigned spins = 0;
   int ok = 1;
@@ -1188,22 +1156,6 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
 
   // ---- wave 0: the broadcast (8 entries per lane pair: entry q = 32 k + lane / 2, first lanes)
   double pc = 0.0;  // -w'_{r+1} . B^{r-1} of this workgroup's entry (wave 0)
-  // Scaled coefficient vector in the layout of wave 0's poll (entry 32 k + lane / 2 in register k
-  // of the first lane of each pair) from raw rows in LDS: the v part scaled by c'_{tv} over
-  // nJ(tv) entries, the u part by c_{tu} over nI(tu) entries (u owners only), zero elsewhere.
-  auto load_w = [&](double* Wv, const double* raw, bool has, int64_t tv, int64_t tu) {
-    const int nv = has && (v_owner || u_owner) ? nJ_of(tv) : 0;
-    const int nu = has && u_owner ? nI_of(tu) : 0;
-    const double cv = cc_of(tv), cu = cr_of(tu);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int q = k * 32 + (lane >> 1);
-      const bool inv = first && q < nv, inu = first && q >= MJ && q - MJ < nu;
-      const double rw = (inv || inu) ? raw[q] : 0.0;
-      Wv[k] = (inv ? cv : cu) * rw;
-    }
-  };
-
   // Copies for later rounds, one wave each (all loads issued before any is written to LDS; the
   // waves have nothing else on their path until the round's end): the column slab of J_t in
   // 16-byte chunks, the row slab of I_t in dwords, the raw rows of w_t and w'_{t+1} in doubles.
@@ -1254,32 +1206,27 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
     }
     row_direct(t, 64 * kPipeStage, lane, 64);
   };
-  auto copy_w = [&](int t) {  // w_t and w'_{t+1}
-    PipeDraw d[5];
+  auto copy_wv = [&](int t) {  // W_t and W'_{t+1} (entries lane + 64 k; E <= 256)
+    const WSrc va = wsrc(t, false), vb = wsrc(t + 1, true);
+    double xa[4], xb[4];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) d[q] = drw(t - 2 + q);  // t - 2 .. t + 2
-    Seg S;
-    seg_clear(S);
-    segs_w(S, t, d);
-    segs_wp(S, t + 1, d + 1);
-    const int tot = S.l0 + S.l1 + S.l2 + S.l3;
-    double v[kPipeStage / 2];
-    int at[kPipeStage / 2];
+    for (int k = 0; k < 4; ++k) {
+      const int q = lane + 64 * k;
+      const double* pa = wsrc_at(va, q);
+      const double* pb = wsrc_at(vb, q);
+      xa[k] = pa ? *(gdouble*)pa : 0.0;
+      xb[k] = pb ? *(gdouble*)pb : 0.0;
+    }
+    double* da = wr_of(t);
+    double* db = wpr_of(t + 1);
 #pragma unroll
-    for (int k = 0; k < kPipeStage / 2; ++k) {
-      at[k] = -1;
-      if (lane + 64 * k < tot) {
-        const double* src;
-        double* dst;
-        seg_at(S, lane + 64 * k, src, dst);
-        v[k] = *(gdouble*)src;
-        at[k] = (int)(dst - lds);
+    for (int k = 0; k < 4; ++k) {
+      const int q = lane + 64 * k;
+      if (q < E) {
+        da[q] = wscale(va, q) * xa[k];
+        db[q] = wscale(vb, q) * xb[k];
       }
     }
-#pragma unroll
-    for (int k = 0; k < kPipeStage / 2; ++k)
-      if (at[k] >= 0) lds[at[k]] = v[k];
-    seg_direct(S, 64 * (kPipeStage / 2), lane, 64);
   };
 
   // ---------------- prologue
@@ -1293,18 +1240,17 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   }
   lds_barrier();
   {
-    // slabs of J_1..J_4 and I_1..I_3; raw rows of w_1, w_2, w'_2, w'_3 (direct copies)
+    // slabs of J_1..J_4 and I_1..I_3; W_1, W_2, W'_2, W'_3
     for (int64_t t = 1; t <= 4; ++t) col_direct(t, 0, tid, T);
     for (int64_t t = 1; t <= 3; ++t) row_direct(t, 0, tid, T);
-    Seg P;  // at most two segments per vector
     for (int v = 0; v < 4; ++v) {
       const int t = v < 2 ? 1 + v : v;
-      PipeDraw d[4];
-      for (int q = 0; q < 4; ++q) d[q] = drw(t - 2 + q);
-      seg_clear(P);
-      if (v < 2) segs_w(P, t, d);
-      else segs_wp(P, t, d);
-      seg_direct(P, 0, tid, T);
+      const WSrc src = wsrc(t, v >= 2);
+      double* dst = v < 2 ? wr_of(t) : wpr_of(t);
+      for (int q = tid; q < E; q += T) {
+        const double* pq = wsrc_at(src, q);
+        dst[q] = pq ? wscale(src, q) * *(gdouble*)pq : 0.0;
+      }
     }
   }
   lds_barrier();
@@ -1328,7 +1274,7 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   if (!ok) s_ok = 0;
   lds_barrier();
   if (tid < 64) {
-    if (e_own >= 0 && need(0, e_own) && lane < kCopies) {
+    if (e_own >= 0 && e_own < EU && lane < kCopies) {
       unsigned long long* S0 = gs.gsum + (size_t)(1 % kGridSumRing) * kCopies * V2;
       st_tagged(S0 + (size_t)lane * V2, e_own, gat[0], 1u);
     }
@@ -1366,71 +1312,75 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   };
 
   if (tid < 64) {
-    // ---- wave 0: poll B^r, publish this workgroup's entry of B^{r+1}, hand B^r over.  W1 and W2
-    // hold w_{r+1} and w'_{r+2} of this workgroup's entry, scaled, in the layout of the poll.
-    double W1[8], W2[8];
-    load_w(W1, wr + (size_t)(1 & 1) * E, need(1, e_own), 1, 0);
-    load_w(W2, wpr + (size_t)(2 & 1) * E, need(2, e_own), 1, 0);
+    // ---- wave 0: poll B^r, publish this workgroup's entry of B^{r+1}, hand B^r over.  Every
+    // owner of an entry in use publishes it every round (zero when no one reads it: its
+    // coefficient vectors and its gathered sum are zero then), so the poll waits for all of them.
+    const bool owner = e_own >= 0 && e_own < EU;
     for (int r = 0; alive; ++r) {
       const unsigned epB = (unsigned)(r + 1);
       const unsigned long long* Sg =
           gs.gsum + (size_t)(epB % kGridSumRing) * kCopies * V2 + (size_t)(w % kCopies) * V2;
-      unsigned needm = 0;  // entries of B^r this lane reads, one bit per register
-      {
-        const int nJn = nJ_of(r + 1), nIr = nI_of(r);
-        const bool er = err_round(r);
+      unsigned long long wd[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int q = k * 32 + (lane >> 1);
+        wd[k] = ld_u64(Sg + (size_t)2 * (q < E ? q : E - 1) + p2);
+      }
+      // while the loads are in flight: W_{r+1} and W'_{r+2} of this workgroup's entry in the
+      // layout of the poll (entry 32 k + lane / 2 in register k)
+      double W1[8], W2[8];
+      if (owner) {
+        const double* w1 = wr_of(r + 1);
+        const double* w2 = wpr_of(r + 2);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int q = k * 32 + (lane >> 1);
-          if (q < E && need_d(q, nJn, nIr, er)) needm |= 1u << k;
+          W1[k] = q < E ? w1[q] : 0.0;
+          W2[k] = q < E ? w2[q] : 0.0;
         }
       }
-      const bool any = __any(needm != 0);
-      const bool publish = e_own >= 0 && need(r + 1, e_own);
-      // the gathered sum of round r + 1, if the helpers have it already
-      const bool early = publish && __hip_atomic_load(&s_gflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= r + 1;
-      double g = early ? gat[(r + 1) & 1] : 0.0;
-      unsigned long long wd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      auto arrived = [&]() -> bool {  // every entry in use carries the epoch of B^r
+        bool mine = true;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int q = k * 32 + (lane >> 1);
+          const unsigned tg = first ? (unsigned)(wd[k] >> 32) : (unsigned)wd[k];
+          mine = mine && (q >= EU || tg == epB);
+        }
+        return __all(mine);
+      };
       spins = 0;
-      while (any && ok) {
+      while (ok && !arrived()) {
+        if (give_up()) ok = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int q = k * 32 + (lane >> 1);
           wd[k] = ld_u64(Sg + (size_t)2 * (q < E ? q : E - 1) + p2);
         }
-        bool mine = true;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const unsigned tg = first ? (unsigned)(wd[k] >> 32) : (unsigned)wd[k];
-          mine = mine && (((needm >> k) & 1u) == 0 || tg == epB);
-        }
-        if (__all(mine)) break;
-        if (give_up()) ok = 0;
       }
       double vals[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
+        const int q = k * 32 + (lane >> 1);
         const unsigned long long o = mirror_word(wd[k]);
-        vals[k] = (first && ((needm >> k) & 1u)) ? tag_value(wd[k], o) : 0.0;
+        vals[k] = (first && q < EU) ? tag_value(wd[k], o) : 0.0;
       }
-      if (publish) {
-        double d = 0.0;
+      if (owner) {
+        double d = 0.0, d2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) d += W1[k] * vals[k];  // w_{r+1} . B^r
-        d = group_sum(d, 64);
-        if (!early) {
-          wait_flag(&s_gflag, (int)(r + 1));
-          g = gat[(r + 1) & 1];
+        for (int k = 0; k < 8; ++k) {
+          d += W1[k] * vals[k];   // w_{r+1} . B^r
+          d2 += W2[k] * vals[k];  // w'_{r+2} . B^r
         }
+        d = group_sum(d, 64);
+        wait_flag(&s_gflag, (int)(r + 1));
+        const double g = gat[(r + 1) & 1];
         if (lane < kCopies) {
           unsigned long long* Sn = gs.gsum + (size_t)((r + 2) % kGridSumRing) * kCopies * V2;
           st_tagged(Sn + (size_t)lane * V2, e_own, g + pc - d, (unsigned)(r + 2));
         }
+        pc = -group_sum(d2, 64);
       }
-      double d2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) d2 += W2[k] * vals[k];  // w'_{r+2} . B^r
-      pc = -group_sum(d2, 64);
       double* Bn = bv + (size_t)(r % 3) * E;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -1449,9 +1399,6 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
         last_k = a.k0 + K;
         break;
       }
-      // w_{r+2} and w'_{r+3}, both applied to B^{r+1}
-      load_w(W1, wr + (size_t)((r + 2) & 1) * E, need(r + 2, e_own), r + 2, r + 1);
-      load_w(W2, wpr + (size_t)((r + 3) & 1) * E, need(r + 3, e_own), r + 2, r + 1);
     }
   } else {
     // ---- waves 1..3: round r of the helpers, after B^r is in LDS
@@ -1494,16 +1441,14 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
       } else if (wv == 3) {
         // the owner's sum of round r + 2 (wave 0 needs it for its next entry), then the column
         // slab of J_{r+5}
-        if (need(r + 2, e_own)) {
-          const double g = gather(r + 2, e_own);
-          if (lane == 0) gat[(r + 2) & 1] = g;
-        }
+        const double g = need(r + 2, e_own) ? gather(r + 2, e_own) : 0.0;
+        if (lane == 0) gat[(r + 2) & 1] = g;
         set_flag(&s_gflag, (int)(r + 2));
         copy_col(r + 5);
       } else if (wv == 4) {
         copy_row(r + 4, []() {});  // the row slab of I_{r+4}
       } else if (wv == 7) {
-        copy_w(r + 3);  // the raw rows of w_{r+3} and w'_{r+4}
+        if (v_owner || u_owner) copy_wv(r + 3);  // W_{r+3} and W'_{r+4}
       }
     }
   }
