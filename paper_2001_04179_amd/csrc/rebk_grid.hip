@@ -1159,19 +1159,18 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   // Copies for later rounds, one wave each (all loads issued before any is written to LDS; the
   // waves have nothing else on their path until the round's end): the column slab of J_t in
   // 16-byte chunks, the row slab of I_t in dwords, the raw rows of w_t and w'_{t+1} in doubles.
-  auto copy_col = [&](int t) {
+  // (in two parts: the loads, then the stores into LDS, so other work can wait between them)
+  auto col_issue = [&](int t, u32x4* v, int* at) -> int {  // returns the chunk count
     const int ncol = nr > 0 ? nJ_of(t) * c16 : 0;
-    if (ncol == 0) return;
+#pragma unroll
+    for (int k = 0; k < kPipeStage / 4; ++k) at[k] = -1;
+    if (ncol == 0) return 0;
     const char* src = colsrc(t);
     const int64_t cstride = a.ldc * esz;
-    u32x4* const dst = (u32x4*)colslab(t);
-    u32x4 v[kPipeStage / 4];
-    int at[kPipeStage / 4];
     int c = lane / c16, p = lane - c * c16;
     const int sc = 64 / c16, sp = 64 - sc * c16;
 #pragma unroll
     for (int k = 0; k < kPipeStage / 4; ++k) {
-      at[k] = -1;
       if (lane + 64 * k < ncol) {
         v[k] = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
         at[k] = c * c16 + p;
@@ -1183,6 +1182,10 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
         ++c;
       }
     }
+    return ncol;
+  };
+  auto col_write = [&](int t, const u32x4* v, const int* at, int ncol) {
+    u32x4* const dst = (u32x4*)colslab(t);
 #pragma unroll
     for (int k = 0; k < kPipeStage / 4; ++k)
       if (at[k] >= 0) dst[at[k]] = v[k];
@@ -1439,12 +1442,15 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
         const int nIt = nI_of(r + 3), lh = (nIt + 1) / 2;
         part_u(r + 3, xc, zc, (int)(r + 1), h == 0 ? 0 : lh, h == 0 ? lh : nIt, h == 0);
       } else if (wv == 3) {
-        // the owner's sum of round r + 2 (wave 0 needs it for its next entry), then the column
-        // slab of J_{r+5}
+        // the owner's sum of round r + 2 (wave 0 needs it for its next entry), with the loads of
+        // the column slab of J_{r+5} in flight meanwhile
+        u32x4 cv[kPipeStage / 4];
+        int cat[kPipeStage / 4];
+        const int ncol = col_issue(r + 5, cv, cat);
         const double g = need(r + 2, e_own) ? gather(r + 2, e_own) : 0.0;
         if (lane == 0) gat[(r + 2) & 1] = g;
         set_flag(&s_gflag, (int)(r + 2));
-        copy_col(r + 5);
+        col_write(r + 5, cv, cat, ncol);
       } else if (wv == 4) {
         copy_row(r + 4, []() {});  // the row slab of I_{r+4}
       } else if (wv == 7) {
