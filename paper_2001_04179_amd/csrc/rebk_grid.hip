@@ -730,11 +730,13 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 // Round t broadcasts B^t = (v^{t+1}, u^t) (and, when a check is due, ||x^{t-3} - x_ref||^2), one
 // entry per owning workgroup.  An entry is P^t (the bracket, summed over workgroups: partial sums
 // of state two and three iterations old) minus w'_t . B^{t-2} minus w_t . B^{t-1}, where w'_t and
-// w_t are the scaled rows of H, G and A above, laid out like B.  Wave 0 of the owner holds w_t and
-// w'_{t+1} in registers; as soon as it has polled B^{t-1} it forms its entry of B^t and publishes
-// it, with no workgroup barrier in between, then hands B^{t-1} to waves 1..3.  Those waves, one
-// round behind, update z and x, publish the partial sums of round t + 2, gather the owner's sum of
-// round t + 1 and stage the slabs and rows of later rounds through registers.
+// w_t are the scaled rows of H, G and A above, laid out like B.  Every owner of an entry in use
+// publishes it every round (zero when no one reads it).  Wave 0 of the owner reads w_t and
+// w'_{t+1} from LDS while its poll of B^{t-1} is in flight; as soon as the poll is complete it forms
+// its entry of B^t and publishes it, with no workgroup barrier in between, then hands B^{t-1} to
+// the other waves.  Those waves, one round behind, update z and x, publish the partial sums of
+// round t + 2, gather the owner's sum of round t + 1 and stage the slabs and the scaled rows of
+// later rounds through registers.
 constexpr int kPipeSlabs = 5;   // slab buffers of each kind (a slab is read in two rounds three apart)
 constexpr int kPipeParts = 4;   // partial vectors kept per workgroup (round t in slot t & 3)
 constexpr int kPipeStage = 32;  // dwords a helper lane holds in flight per round (the rest: direct copies)
@@ -752,8 +754,9 @@ __host__ __device__ inline PipeLayout pipe_layout(int64_t m, int64_t n, int MI, 
   L.NR = (int)((m + G - 1) / G) + 16 / esz;
   L.NC = (int)((n + G - 1) / G) + kColOwnAlign;
   L.NRS = L.NR + 16 / esz;
-  // z history (4 NR), b (NR), x history (4 NC), x_ref (NC), three broadcast vectors, raw rows of
-  // w_t and w'_t (two of each), two gathered sums; an even count keeps the slabs 16-byte aligned
+  // z history (4 NR), b (NR), x history (4 NC), x_ref (NC), three broadcast vectors, the scaled
+  // vectors W_t and W'_t (two of each), two gathered sums; an even count keeps the slabs 16-byte
+  // aligned
   L.dbl = (5 * (size_t)L.NR + 5 * (size_t)L.NC + 7 * (size_t)E + 2 + 1) & ~(size_t)1;
   L.slabC = ((size_t)L.NRS * MJ + 7) / 8 * 8;
   L.slabR = ((size_t)L.NC * MI + 7) / 8 * 8;
@@ -858,8 +861,8 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   double* xh = bl + L.NR;         // x^t on owned columns at xh + (t & 3) NC
   double* xr = xh + 4 * L.NC;     // x_ref on owned columns
   double* bv = xr + L.NC;         // B^t at bv + (t % 3) E
-  double* wr = bv + 3 * E;        // raw rows of w_t at wr + (t & 1) E (v part at 0, u part at MJ)
-  double* wpr = wr + 2 * E;       // raw rows of w'_t at wpr + (t & 1) E
+  double* wr = bv + 3 * E;        // W_t at wr + (t & 1) E (v part at 0, u part at MJ)
+  double* wpr = wr + 2 * E;       // W'_t at wpr + (t & 1) E
   double* gat = wpr + 2 * E;      // gathered sum of round t at gat[t & 1]
   TP* slabC = (TP*)(lds + L.dbl); // column slab of J_t at slabC + (t % 5) slabC (runs of nrs)
   TP* slabR = slabC + kPipeSlabs * L.slabC;
@@ -1156,10 +1159,10 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
 
   // ---- wave 0: the broadcast (8 entries per lane pair: entry q = 32 k + lane / 2, first lanes)
   double pc = 0.0;  // -w'_{r+1} . B^{r-1} of this workgroup's entry (wave 0)
-  // Copies for later rounds, one wave each (all loads issued before any is written to LDS; the
-  // waves have nothing else on their path until the round's end): the column slab of J_t in
-  // 16-byte chunks, the row slab of I_t in dwords, the raw rows of w_t and w'_{t+1} in doubles.
-  // (in two parts: the loads, then the stores into LDS, so other work can wait between them)
+  // Copies for later rounds, one wave each, all loads issued before any is written to LDS: the
+  // column slab of J_t in 16-byte chunks (in two parts, the loads and then the stores into LDS, so
+  // the gather can run between them), the row slab of I_t in dwords, and the scaled vectors
+  // W_t, W'_{t+1} in doubles.
   auto col_issue = [&](int t, u32x4* v, int* at) -> int {  // returns the chunk count
     const int ncol = nr > 0 ? nJ_of(t) * c16 : 0;
 #pragma unroll
