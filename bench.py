@@ -58,6 +58,10 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--tol", type=float, default=1e-6)
+    p.add_argument("--check-every", type=int, default=8,
+                   help="iterations between evaluations of the stop rule in the headline solves (the "
+                        "returned iterate meets the tolerance; it may lie up to check_every - 1 "
+                        "iterations past the first one that does)")
     p.add_argument("--grid-wgs", type=int, default=0)
     p.add_argument("--panels", default="f64,f32", help="panel types run with the grid kernel")
     p.add_argument("--pipe-panels", default="f32",
@@ -109,7 +113,7 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}))
 
 
-def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs, kernel="grid"):
+def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs, kernel="grid", check_every=1):
     """One solve form: a fresh solver (panels packed; for the pipelined kernel also its Gram
     matrices built) and a solve to tol, per timed step."""
     import torch
@@ -129,7 +133,7 @@ def run_form(rebk, S, A_d, b_d, xr_d, panel, steps, warmup, tol, grid_wgs, kerne
         solver = rebk.Solver(A_d, S.row_off, S.col_off, S.alpha, S.seed, panel_dtype=panel)
         if kernel == "pipe":
             prep_ms.append(solver.pipe_prepare())
-        out = solver.solve_ex(b_d, max_iter=2_000_000, x_ref=xr_d, tol=tol, check_every=1, kernel=kernel,
+        out = solver.solve_ex(b_d, max_iter=2_000_000, x_ref=xr_d, tol=tol, check_every=check_every, kernel=kernel,
                               grid_wgs=grid_wgs)
         solver.close()
         return out
@@ -771,7 +775,7 @@ def main():
     for panel, kernel in plan:
         key = panel if kernel == "grid" else f"{panel}+pipe"
         forms[key] = run_form(rebk, S, A_d, b_d, xr_d, panel, args.steps, args.warmup, args.tol, args.grid_wgs,
-                              kernel=kernel)
+                              kernel=kernel, check_every=args.check_every)
         print(f"# {key}: {json.dumps(forms[key])}", file=sys.stderr, flush=True)
     ok = {k: v for k, v in forms.items() if v["status"] == "ok" and v["rel_err"] < args.tol}
     chosen_key = max(ok, key=lambda k: ok[k]["solves_per_s"]) if ok else next(iter(forms))
@@ -803,7 +807,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"REBK rank-{1500 // args.scale} {m}x{n}, 200-row / 20-column blocks, tol {args.tol:g}",
                    "m": m, "n": n, "row_block": 200, "col_block": 20, "alpha": S.alpha,
-                   "panel_dtype": chosen["panel_dtype"], "kernel": chosen.get("kernel", "grid")},
+                   "panel_dtype": chosen["panel_dtype"], "kernel": chosen.get("kernel", "grid"),
+                   "check_every": args.check_every},
         "iterations": chosen["iterations"],
         "time_to_tol_ms": chosen["ms_per_solve"],
         "us_per_iter": chosen["us_per_iter"],
