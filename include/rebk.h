@@ -81,7 +81,8 @@ typedef enum {
 typedef enum {
     REBK_KERNEL_AUTO = 0,     /* WORKGROUP for tiny systems (m |J| + |I| n + 4 (m + n) <= 8192); else PIPE
                                  when its Gram matrices exist (rebk_pipe_prepare, or an earlier
-                                 PIPE solve on the handle) and the call fits its limits; else GRID */
+                                 PIPE solve on the handle), the panels are narrower than FP64 and
+                                 the call fits its limits; else GRID */
     REBK_KERNEL_WORKGROUP = 1,/* one workgroup runs the whole solve (small systems) */
     REBK_KERNEL_GRID = 2,     /* one persistent cooperative grid, one grid-wide reduction per
                                  iteration; needs ceil(n / grid) + 8 <= 256 owned columns, blocks

@@ -301,11 +301,14 @@ int run_iterations(rebk_handle* h, rebk::SolveArgs a, int kernel, int grid_wgs, 
     // and x.  Measured on MI355X: 5.7 us vs 7.3 us (whole chip) at 250 x 120 with 10 x 10 blocks,
     // 8.7 vs 7.5 at 500 x 250, 23 vs 8 at 1000 x 100 with 100 x 10 blocks.  Past that the
     // pipelined kernel, once its Gram matrices exist (rebk_pipe_prepare or an earlier pipelined
-    // solve), where it fits: 5.0 us vs 7.8 us per iteration on the 20000 x 2000 workload.
+    // solve), where it fits: 3.6 us vs 7.8 us per iteration on the 20000 x 2000 workload with FP32
+    // panels.  Not for FP64 panels: their slabs are twice the bytes its copy waves stage, and it
+    // measured 9.5 us there against 8.3 us for the grid kernel.
     const double work = (double)h->m * h->max_nJ + (double)h->n * h->max_nI + 4.0 * (double)(h->m + h->n);
     if (wg_fits(h, a) && work <= 8192.0)
       kernel = REBK_KERNEL_WORKGROUP;
-    else if (!fixed && h->pipe_G && pipe_fits(h, a, grid_wgs > 0 ? grid_wgs : h->cus, nullptr))
+    else if (!fixed && h->pipe_G && h->panel_dtype != REBK_F64 &&
+             pipe_fits(h, a, grid_wgs > 0 ? grid_wgs : h->cus, nullptr))
       kernel = REBK_KERNEL_PIPE;
     else
       kernel = REBK_KERNEL_GRID;

@@ -739,7 +739,12 @@ __global__ void __launch_bounds__(kGridThreads) grid_solve_kernel(SolveArgs a, G
 // later rounds through registers.
 constexpr int kPipeSlabs = 5;   // slab buffers of each kind (a slab is read in two rounds three apart)
 constexpr int kPipeParts = 4;   // partial vectors kept per workgroup (round t in slot t & 3)
-constexpr int kPipeStage = 32;  // dwords a helper lane holds in flight per round (the rest: direct copies)
+// dwords a helper lane holds in flight per round (the rest: direct copies); with FP64 panels more
+// than this pushes the kernel past 256 VGPRs into scratch
+template <typename TP>
+constexpr int pipe_stage() {
+  return 32;
+}
 static_assert(kPipeMaxStride == 256, "wave 0 holds a broadcast vector in 8 registers per lane pair");
 
 struct PipeLayout {
@@ -751,8 +756,16 @@ struct PipeLayout {
 
 __host__ __device__ inline PipeLayout pipe_layout(int64_t m, int64_t n, int MI, int MJ, int E, int G, int esz) {
   PipeLayout L;
-  L.NR = (int)((m + G - 1) / G) + 16 / esz;
-  L.NC = (int)((n + G - 1) / G) + kColOwnAlign;
+  // the most rows / columns a workgroup owns: inner ownership boundaries are multiples of al
+  // rounded down from floor(w total / G), so two inner ones lie at most al ceil(ceil(total / G) / al)
+  // apart; the last range ends at total itself
+  auto most = [G](int64_t total, int al) -> int {
+    const int64_t q = (total + G - 1) / G;
+    const int64_t inner = (q + al - 1) / al * al, last = total - own_lo(G - 1, total, G, al);
+    return (int)(inner > last ? inner : last);
+  };
+  L.NR = most(m, 16 / esz);
+  L.NC = most(n, kColOwnAlign);
   L.NRS = L.NR + 16 / esz;
   // z history (4 NR), b (NR), x history (4 NC), x_ref (NC), three broadcast vectors, the scaled
   // vectors W_t and W'_t (two of each), two gathered sums; an even count keeps the slabs 16-byte
@@ -1166,14 +1179,14 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   auto col_issue = [&](int t, u32x4* v, int* at) -> int {  // returns the chunk count
     const int ncol = nr > 0 ? nJ_of(t) * c16 : 0;
 #pragma unroll
-    for (int k = 0; k < kPipeStage / 4; ++k) at[k] = -1;
+    for (int k = 0; k < pipe_stage<TP>() / 4; ++k) at[k] = -1;
     if (ncol == 0) return 0;
     const char* src = colsrc(t);
     const int64_t cstride = a.ldc * esz;
     int c = lane / c16, p = lane - c * c16;
     const int sc = 64 / c16, sp = 64 - sc * c16;
 #pragma unroll
-    for (int k = 0; k < kPipeStage / 4; ++k) {
+    for (int k = 0; k < pipe_stage<TP>() / 4; ++k) {
       if (lane + 64 * k < ncol) {
         v[k] = *(gdword4*)(src + (int64_t)c * cstride + 16 * p);
         at[k] = c * c16 + p;
@@ -1190,27 +1203,27 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
   auto col_write = [&](int t, const u32x4* v, const int* at, int ncol) {
     u32x4* const dst = (u32x4*)colslab(t);
 #pragma unroll
-    for (int k = 0; k < kPipeStage / 4; ++k)
+    for (int k = 0; k < pipe_stage<TP>() / 4; ++k)
       if (at[k] >= 0) dst[at[k]] = v[k];
-    if (ncol > 64 * (kPipeStage / 4)) col_direct(t, 64 * (kPipeStage / 4), lane, 64);
+    if (ncol > 64 * (pipe_stage<TP>() / 4)) col_direct(t, 64 * (pipe_stage<TP>() / 4), lane, 64);
   };
   auto copy_row = [&](int t, auto&& between) {  // `between` runs while the loads are in flight
     const int nrow = row_dwords(t);
-    uint32_t v[kPipeStage];
+    uint32_t v[pipe_stage<TP>()];
     if (nrow > 0) {
       gdword* src = (gdword*)rowsrc(t);
 #pragma unroll
-      for (int k = 0; k < kPipeStage; ++k)
+      for (int k = 0; k < pipe_stage<TP>(); ++k)
         if (lane + 64 * k < nrow) v[k] = src[lane + 64 * k];
     }
     between();
     if (nrow > 0) {
       uint32_t* const dst = (uint32_t*)rowslab(t);
 #pragma unroll
-      for (int k = 0; k < kPipeStage; ++k)
+      for (int k = 0; k < pipe_stage<TP>(); ++k)
         if (lane + 64 * k < nrow) dst[lane + 64 * k] = v[k];
     }
-    row_direct(t, 64 * kPipeStage, lane, 64);
+    row_direct(t, 64 * pipe_stage<TP>(), lane, 64);
   };
   auto copy_wv = [&](int t) {  // W_t and W'_{t+1} (entries lane + 64 k; E <= 256)
     const WSrc va = wsrc(t, false), vb = wsrc(t + 1, true);
@@ -1447,8 +1460,8 @@ __global__ void __launch_bounds__(kPipeThreads) pipe_solve_kernel(SolveArgs a, G
       } else if (wv == 3) {
         // the owner's sum of round r + 2 (wave 0 needs it for its next entry), with the loads of
         // the column slab of J_{r+5} in flight meanwhile
-        u32x4 cv[kPipeStage / 4];
-        int cat[kPipeStage / 4];
+        u32x4 cv[pipe_stage<TP>() / 4];
+        int cat[pipe_stage<TP>() / 4];
         const int ncol = col_issue(r + 5, cv, cat);
         const double g = need(r + 2, e_own) ? gather(r + 2, e_own) : 0.0;
         if (lane == 0) gat[(r + 2) & 1] = g;

@@ -118,9 +118,12 @@ def test_pipe_prepare_and_release(rebk, cfg1):
 
 def test_auto_picks_pipe_once_prepared(rebk, oracle_lib, cfg1):
     """AUTO runs the grid kernel until the Gram matrices exist, the pipelined kernel after
-    rebk_pipe_prepare (same iterates), and the grid kernel again after rebk_pipe_release."""
+    rebk_pipe_prepare (same iterates), and the grid kernel again after rebk_pipe_release; all with
+    FP32 panels.  With FP64 panels AUTO stays on the grid kernel (faster there), while an explicit
+    pipelined request still runs it."""
     S = cfg1
-    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    A32 = W.round_to_f32(S.A)
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed, panel_dtype="f32")
     a = solver.solve_ex(to_dev(S.b), max_iter=300)
     assert a["result"].kernel == "grid"
     solver.pipe_prepare()
@@ -133,8 +136,17 @@ def test_auto_picks_pipe_once_prepared(rebk, oracle_lib, cfg1):
     c = solver.solve_ex(to_dev(S.b), max_iter=300)
     solver.close()
     assert c["result"].kernel == "grid"
-    ref = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=300)
+    ref = oracle_lib.rebk_solve(A32, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=300)
     for o in (a, b, c):
+        assert rel(o["x"].cpu().numpy(), ref["x"]) <= RTOL_F64
+    solver = rebk.Solver(to_dev(S.A), S.row_off, S.col_off, S.alpha, S.seed)
+    solver.pipe_prepare()
+    d = solver.solve_ex(to_dev(S.b), max_iter=300)
+    e = solver.solve_ex(to_dev(S.b), max_iter=300, kernel="pipe")
+    solver.close()
+    assert d["result"].kernel == "grid" and e["result"].kernel == "pipe"
+    ref = oracle_lib.rebk_solve(S.A, S.row_off, S.col_off, S.alpha, S.seed, S.b, max_iter=300)
+    for o in (d, e):
         assert rel(o["x"].cpu().numpy(), ref["x"]) <= RTOL_F64
 
 
