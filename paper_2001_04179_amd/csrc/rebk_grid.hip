@@ -1,7 +1,9 @@
-// Persistent cooperative REBK kernel for gfx950 (Du, Si, Sun, arXiv:2001.04179, Algorithm 1).
+// Persistent cooperative REBK kernels for gfx950 (Du, Si, Sun, arXiv:2001.04179, Algorithm 1): the
+// grid kernel below, and after it the pipelined kernel (one broadcast hop per iteration).
 //
-// Ownership: workgroup w owns rows [w*m/G, (w+1)*m/G) of z and columns [w*n/G, (w+1)*n/G) of x;
-// both stay in LDS for the whole launch.  One grid-wide reduction per iteration carries
+// Ownership: workgroup w owns rows [w*m/G, (w+1)*m/G) of z and columns [w*n/G, (w+1)*n/G) of x,
+// each boundary rounded down to 16 bytes of panel entries (rows) or 8 columns (own_lo); both stay
+// in LDS for the whole launch.  One grid-wide reduction per iteration carries
 //   - the partial sums of v^{k+1} = A_{:,J_{k+1}}^T z^k over owned rows,
 //   - the partial sums of u^k = A_{I_k,:} x^{k-1} - b_{I_k} + z^k_{I_k} (owned columns, plus
 //     z - b on owned rows), and
