@@ -94,10 +94,12 @@ typedef enum {
                                  grid-wide broadcast per iteration is on the critical path.  Builds
                                  A A^T, A^T A and a row-major copy of A in FP64 on first use
                                  (8 (m^2 + n^2 + m n) bytes, kept until rebk_destroy or
-                                 rebk_pipe_release; see rebk_pipe_prepare).  Same limits as GRID,
-                                 plus max|I| + max|J| + 1 <= the grid size and <= 256 (after
-                                 rounding up to a multiple of 32); no refinement steps
-                                 (rebk_solve_refined) */
+                                 rebk_pipe_release; see rebk_pipe_prepare).  The column limits
+                                 of GRID; its own LDS layout (5 slabs of each kind, sized by the
+                                 most rows and columns a workgroup owns) within 150 KB;
+                                 max|I| + max|J| + 1 <= the grid size and <= 256 (after rounding
+                                 up to a multiple of 32); all workgroups co-resident; no
+                                 refinement steps (rebk_solve_refined) and no static workspace */
 } rebk_kernel_t;
 
 typedef struct {
